@@ -1,0 +1,194 @@
+"""Benchmark: the order-6 FP32 curvilinear layered workload on one GPU.
+
+One step = five Runge-Kutta stages of the full semi-discrete right-hand side
+(volume terms, boundary penalties, point source) fused with the stage update,
+plus the receiver gather.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 2000] [--warmup 20] [--no-cpu]
+
+The metric is Mpts*stage/s (grid points times Runge-Kutta stages per
+second); the roofline object reports the stage kernel's achieved algorithmic
+HBM bandwidth against the 8 TB/s peak; cpu_baseline times the CPU oracle on
+a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+# algorithmic words per node per stage: read Q_in (9) + coefficients (12),
+# read the Runge-Kutta register (9, stages 2-5 only), write it (9) and Q_out (9)
+WORDS_STAGE1 = 9 + 12 + 9 + 9
+WORDS_STAGE = WORDS_STAGE1 + 9
+WORDS_AVG = (WORDS_STAGE1 + 4 * WORDS_STAGE) / 5.0
+PROFILE = os.path.join(ROOT, "profiles", "stage_kernel_topo_layer_257x257x193.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_2011_02600_amd", "csrc", "kernels.hip")
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(nodes):
+    """HBM bytes per stage launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source (else None)."""
+    if not os.path.exists(PROFILE):
+        return None
+    vals = {}
+    for line in open(PROFILE):
+        line = line.strip().lstrip("-* ")
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256_16") != kernel_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(wl, nstages=2):
+    """The CPU oracle as it stands, timed on the host: `nstages` Runge-Kutta
+    stages (right-hand side + stage update) of the full workload."""
+    import numpy as np
+    from oracle import elastic as E
+    from oracle import lsrk
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    blk = E.Block(wl["xyz"], wl["order"]).set_material(wl["rho"], wl["cp"], wl["cs"])
+    src = E.Source(blk, wl["src_xi"], wl["src_M"], E.STF_RICKER, wl["src_f0"], wl["src_t0"])
+    Q = np.array(wl["Q0"], dtype=np.float64)
+    dQ = np.zeros_like(Q)
+    dt = wl["dt"]
+    t0 = time.perf_counter()
+    for k in range(nstages):
+        dQ *= lsrk.A_F[k]
+        dQ += dt * E.rhs(blk, Q, lsrk.C_F[k] * dt, wl["gamma"], sources=[src])
+        Q += lsrk.B_F[k] * dQ
+    el = time.perf_counter() - t0
+    nodes = Q[0].size
+    return {"value": nodes * nstages / el / 1e6, "unit": "Mpts*stage/s", "cores": cores, "kind": "oracle",
+            "sample": "%d Runge-Kutta stages (RHS + update) of the full %dx%dx%d workload in float64 numpy, "
+                      "%.1f s; mesh/metric setup excluded" % ((nstages,) + tuple(Q.shape[1:][::-1]) + (el,))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--kernel-steps", type=int, default=200,
+                    help="steps of the stage-kernel-only timing region")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--ty", type=int, default=8)
+    ap.add_argument("--zchunk", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the solver is a single-block, single-GPU build "
+              "(multi-GPU sharding is described in DESIGN.md, not implemented).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2011_02600_amd import sbp
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    print("bench: generating workload", file=sys.stderr, flush=True)
+    wl = W.topo_layer()
+    ns, nr, nq = wl["xyz"].shape[1:]
+    nodes = nq * nr * ns
+    s = sbp.Solver(wl["xyz"], order=6, dtype="f32", gamma=wl["gamma"], device=dev)
+    s.set_material(wl["rho"], wl["cp"], wl["cs"])
+    s.set_launch(args.ty, args.zchunk)
+    s.add_source(wl["src_xi"], wl["src_M"], sbp.SBP_STF_RICKER, wl["src_f0"], wl["src_t0"])
+    s.record(wl["receivers"], args.warmup + args.steps)
+    stream = s.stream
+    dt = wl["dt"]
+    print("bench: warmup", file=sys.stderr, flush=True)
+    s.step(args.warmup, dt)
+    torch.cuda.synchronize()
+
+    # ---- timed region: the whole workload (stages + source + receivers)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    s.step(args.steps, dt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1)
+    secs = ms / 1e3
+    value = nodes * 5 * args.steps / secs / 1e6
+    traces = s.traces.float().cpu().numpy()
+    if not np.all(np.isfinite(traces)):
+        raise RuntimeError("non-finite receiver traces")
+    print("bench: %d steps in %.3f s (events) / %.3f s (wall)" % (args.steps, secs, wall), file=sys.stderr,
+          flush=True)
+
+    # ---- stage kernel alone (same solver, no source, no receivers), events on
+    # the stream the kernels are launched on
+    sbp.sbp_record(s.h, 0, None, None, 0)
+    sbp.sbp_clear_sources(s.h)
+    k0 = torch.cuda.Event(enable_timing=True)
+    k1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    k0.record(stream)
+    s.step(args.kernel_steps, dt)
+    k1.record(stream)
+    torch.cuda.synchronize()
+    launch_ms = k0.elapsed_time(k1) / (5 * args.kernel_steps)
+    bytes_per_launch = WORDS_AVG * 4 * nodes
+    achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9
+    traffic = read_traffic(nodes)
+    s.close()
+
+    out = {
+        "metric": "Mpts*stage/s (order-6 FP32 curvilinear RHS + LSRK4 stage update)",
+        "value": round(value, 2),
+        "unit": "Mpts*stage/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "topo_layer: order-6 upwind SBP, curvilinear 257x257x193 (q,r,s) block under "
+                               "seeded topography, 1 km layer over half-space, Ricker moment source, "
+                               "64 surface receivers, CFL 0.5",
+                   "grid": [nq, nr, ns], "nodes": nodes, "order": 6, "dt": dt,
+                   "launch": {"ty": args.ty, "zchunk": args.zchunk}},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic / (launch_ms / 1e3) / 1e9, 1),
+                     "traffic_bytes_per_launch": traffic,
+                     "kernel": "stage_kernel<float,6,%d>" % args.ty,
+                     "avg_launch_ms": round(launch_ms, 4),
+                     "algorithmic_bytes_per_launch": int(bytes_per_launch),
+                     "words_per_node": WORDS_AVG},
+    }
+    if not args.no_cpu:
+        print("bench: cpu oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * sbp.h -- C ABI of the MI355X (gfx950) upwind-SBP elastic wave solver.
+ *
+ * The library advances the semi-discrete 3D velocity-stress elastic wave
+ * equation on one boundary-conforming curvilinear block (Duru, Fung &
+ * Williams, arXiv:2011.02600):
+ *
+ *   P~^{-1} dQ/dt = grad_{D-} . F(Q) + sum_xi B_xi(grad_{D+} Q) + sum SAT   (eq. gen_hyp_transformed_discrete_SAT)
+ *
+ * with the upwind dual-pair SBP operators D+/D- (Sec. 4.1, Table tab:upwind)
+ * applied along the reference axes q, r, s, the metric terms J and
+ * J d(xi)/dx (Sec. 2.2), an isotropic medium rho, lambda, mu (eq. S matrix),
+ * boundary penalties on the six faces (eq. SAT_free_surface, eq. SAT_General
+ * with the hat variables of App. A), point moment-tensor sources
+ * (eq. momententor_pointsource) and the five-stage fourth-order low-storage
+ * Runge-Kutta scheme of Carpenter & Kennedy (Sec. 7).
+ *
+ * Conventions shared by every entry point
+ *  - Every call returns an int: SBP_OK (0) or a negative SBP_E* code.  The
+ *    text of the last failure on the calling thread is sbp_last_error().
+ *    No C++ exception crosses the ABI.
+ *  - Grid functions are dense arrays in (ns, nr, nq) order, q fastest
+ *    ("row-wise" storage of Sec. 4.1 with q innermost).  A state holds the
+ *    nine fields (vx, vy, vz, sxx, syy, szz, sxy, sxz, syz) one after another:
+ *    9 * nq * nr * ns values of the handle's dtype.
+ *  - Host inputs are copied; the caller keeps ownership of every pointer it
+ *    passes.  Device memory is the caller's: all device state lives in the
+ *    workspace given to sbp_init_grid, which must stay allocated until
+ *    sbp_destroy; the library never allocates or frees device memory.
+ *  - Work is queued asynchronously on the HIP stream given at init (NULL: the
+ *    null stream).  Outputs written to device memory are valid once the
+ *    caller has synchronised that stream.  Calls that return host data
+ *    (sbp_get_state to host, sbp_energy) synchronise the stream themselves.
+ *  - A handle is not thread-safe: use one handle per thread/stream.
+ */
+#ifndef SBP_H
+#define SBP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sbp_ctx* sbp_handle;
+
+/* return codes */
+enum {
+    SBP_OK = 0,
+    SBP_EINVAL = -1,    /* invalid argument (sizes, order, gamma, material, ...) */
+    SBP_ENOMEM = -2,    /* workspace too small */
+    SBP_EHIP = -3,      /* a HIP runtime call failed; see sbp_last_error() */
+    SBP_ESTATE = -4,    /* call out of order (e.g. sbp_step before sbp_set_material) */
+    SBP_EUNSTABLE = -5  /* non-finite energy detected */
+};
+
+/* arithmetic type of the device path */
+enum { SBP_F32 = 32, SBP_F64 = 64 };
+
+/* boundary-penalty variant */
+enum {
+    SBP_SAT_CHARACTERISTIC = 0, /* eq. SAT_General with hat variables, all faces */
+    SBP_SAT_TRACTION = 1        /* eq. SAT_free_surface on faces with gamma == 1,
+                                   characteristic penalty on the others */
+};
+
+/* source-time functions */
+enum {
+    SBP_STF_RICKER = 0, /* (1 - 2 a) exp(-a), a = (pi f0 (t - t0))^2 */
+    SBP_STF_EXPT = 1    /* (t - t0) / T^2 exp(-(t - t0) / T) for t >= t0, else 0
+                           (eq. momententor_pointsource, T = 0.1 s in Sec. 7.1) */
+};
+
+/*
+ * Bytes of device workspace a handle needs for an nq x nr x ns grid (points
+ * per axis, the reference axes q, r, s of Sec. 2.2) of interior order
+ * `order` in `dtype`.  Writes the size to *bytes.  Same validation as
+ * sbp_init_grid.
+ */
+int sbp_workspace_bytes(int nq, int nr, int ns, int order, int dtype, size_t* bytes);
+
+/*
+ * Create a solver for one curvilinear block.
+ *  nq, nr, ns   points along q, r, s (uniform reference grid xi_i = i / (n-1),
+ *               Sec. 4.1); each must be >= 2 * order so that the two
+ *               boundary closures of the SBP operators do not overlap.
+ *  xyz          host, 3 * nq * nr * ns doubles: x, then y, then z, each a
+ *               grid function.  NULL selects the identity map of the unit
+ *               cube.  Metric terms are computed on the host in double
+ *               precision (x_xi = D0 x with D0 = (D+ + D-)/2, J = det, and the
+ *               conservative cofactor form of J dxi/dx); a non-positive
+ *               Jacobian anywhere is SBP_EINVAL.
+ *  order        interior order of accuracy of the upwind pair: 2, 4 or 6.
+ *  dtype        SBP_F32 or SBP_F64 (every device array and kernel uses it).
+ *  gamma        host, 6 doubles, reflection coefficient of eq. BC_General2
+ *               per face in the order (q=0, q=1, r=0, r=1, s=0, s=1); each
+ *               in [-1, 1]: 1 free surface, 0 absorbing, -1 clamped.
+ *  sat_variant  SBP_SAT_CHARACTERISTIC or SBP_SAT_TRACTION.
+ *  workspace    device pointer to >= sbp_workspace_bytes() bytes, 256-byte
+ *               aligned, owned by the caller.
+ *  stream       hipStream_t cast to void* (NULL = null stream).
+ * On success *out holds the handle and the state is zero at t = 0.
+ */
+int sbp_init_grid(sbp_handle* out, int nq, int nr, int ns, const double* xyz, int order,
+                  int dtype, const double* gamma, int sat_variant, void* workspace,
+                  size_t workspace_bytes, void* stream);
+
+/*
+ * Set the medium: host grid functions rho, cp, cs (nq*nr*ns doubles each).
+ * mu = rho cs^2, lambda = rho cp^2 - 2 mu (eq. S matrix); requires rho > 0,
+ * mu > 0 and 3 lambda + 2 mu > 0, else SBP_EINVAL.  Impedances for the
+ * penalties are Z_p = rho cp, Z_s = rho cs (Sec. 3).
+ */
+int sbp_set_material(sbp_handle h, const double* rho, const double* cp, const double* cs);
+
+/*
+ * Add a point moment-tensor source (eq. momententor_pointsource):
+ *   d sigma / dt += M g(t) delta_h,
+ *  xi       host, 3 doubles: source position in reference coordinates
+ *           (q, r, s) in [0, 1]^3 (outside: SBP_EINVAL).
+ *  M        host, 6 doubles (Mxx, Myy, Mzz, Mxy, Mxz, Myz).
+ *  stf      SBP_STF_RICKER (param = peak frequency f0) or SBP_STF_EXPT
+ *           (param = T); t0 = time shift.
+ * delta_h is the tensor product of one-dimensional discrete deltas over the
+ * 2(p+1) nodes nearest to xi per axis (Lagrange weights divided by the SBP
+ * norm weights) divided by J; it reproduces the point value of tensor
+ * polynomials of degree < 2(p+1).  At most 4 sources per handle.
+ */
+int sbp_add_source(sbp_handle h, const double* xi, const double* M, int stf, double param,
+                   double t0);
+
+/* Remove all sources. */
+int sbp_clear_sources(sbp_handle h);
+
+/*
+ * Overwrite the state with 9 dense grid functions of the handle's dtype
+ * (q_is_device != 0: device pointer, else host), set the time to t.
+ */
+int sbp_set_state(sbp_handle h, const void* q, int q_is_device, double t);
+
+/*
+ * Copy the state out (same layout as sbp_set_state); *t_out (may be NULL)
+ * receives the current time.  A host destination synchronises the stream.
+ */
+int sbp_get_state(sbp_handle h, void* q, int q_is_device, double* t_out);
+
+/*
+ * Register receivers: nrec node indices (host, 3*nrec ints (i, j, k) along
+ * q, r, s).  After every step the velocity (vx, vy, vz) at each receiver is
+ * written to out_device[(step * nrec + r) * 3 + c] (dtype of the handle),
+ * step counting from 0 at this call, for at most max_steps steps; an
+ * sbp_step call that would exceed max_steps is SBP_EINVAL.  nrec = 0
+ * disables recording.  out_device is owned by the caller.
+ */
+int sbp_record(sbp_handle h, int nrec, const int* ijk, void* out_device, int max_steps);
+
+/*
+ * Advance nsteps steps of size dt (> 0) with the five-stage 2N-storage
+ * Runge-Kutta scheme; every stage evaluates the full right-hand side
+ * (volume terms, penalties, sources) and is fused with the stage update
+ * dQ <- A_k dQ + dt RHS, Q <- Q + B_k dQ.  Asynchronous on the stream.
+ * SBP_ESTATE before sbp_set_material.
+ */
+int sbp_step(sbp_handle h, int nsteps, double dt);
+
+/*
+ * Evaluate the semi-discrete right-hand side dQ/dt of the current state at
+ * time t (sources evaluated at t) into out_device (9 dense grid functions,
+ * handle dtype).  The state and the time are not changed.  Asynchronous.
+ */
+int sbp_rhs(sbp_handle h, void* out_device, double t);
+
+/*
+ * Discrete energy 1/2 <Q, P~^{-1} Q>_H = 1/2 sum H_ijk J (rho |v|^2 +
+ * sigma^T C^{-1} sigma) of the current state (eq. physical_energy_discrete
+ * with the curvilinear weight J), accumulated in double.  Synchronises the
+ * stream.  SBP_EUNSTABLE if the result is not finite.
+ */
+int sbp_energy(sbp_handle h, double* E);
+
+/*
+ * Launch shape of the stage kernel: ty rows of 64 points per thread block
+ * (4 or 8) and zchunk planes per block along s (>= 1; 0 = automatic).
+ * Does not change results beyond floating-point summation order (it does
+ * not change it at all: every node is computed by the same instructions).
+ */
+int sbp_set_launch(sbp_handle h, int ty, int zchunk);
+
+/* Current time and number of completed steps. */
+int sbp_time(sbp_handle h, double* t, long long* steps);
+
+/* Release the handle (not the workspace). */
+int sbp_destroy(sbp_handle h);
+
+/* Text of the last failure on the calling thread ("" if none). */
+const char* sbp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBP_H */

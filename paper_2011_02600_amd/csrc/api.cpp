@@ -1,0 +1,772 @@
+// Host side of the C ABI declared in include/sbp.h: validation, workspace
+// layout, metric terms and material coefficients (double precision on the
+// host), point-source stencils, and the per-stage kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sbp.h"
+#include "internal.hpp"
+#include "kernels.hpp"
+
+using namespace sbp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return fail(SBP_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// Five-stage 2N-storage fourth-order Runge-Kutta coefficients (Carpenter &
+// Kennedy 1994, the integrator named in Sec. 7).
+const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                        -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                        1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                        2277821191437.0 / 14882151754819.0};
+const double kRkC[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 / 6820363962896.0,
+                        2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
+
+constexpr int kMaxRec = 65536;
+constexpr int kMaxPart = 1024;
+constexpr double kPi = 3.14159265358979323846;
+
+std::size_t align256(std::size_t b) { return (b + 255) & ~std::size_t(255); }
+
+struct Geometry {
+  int nq, nr, ns;
+  std::size_t n;
+  std::size_t idx(int i, int j, int k) const { return ((std::size_t)k * nr + j) * nq + i; }
+};
+
+struct Src {
+  int i0, j0, k0;
+  double M[6];
+  int stf;
+  double param, t0;
+};
+
+}  // namespace
+
+struct sbp_ctx {
+  int order = 0, dtype = 0, esize = 0;
+  Geometry g{};
+  Closure cl;
+  double gamma[6] = {};
+  int sat_variant = 0;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  std::size_t ws_bytes = 0;
+  // byte offsets in the workspace
+  std::size_t off_qa = 0, off_qb = 0, off_dq = 0, off_coef = 0, off_face[6] = {}, off_src = 0,
+              off_rec = 0, off_part = 0, off_bounds = 0, total = 0;
+  std::size_t face_n[6] = {};
+  int px = 0;
+  std::size_t plane = 0, field = 0;
+  // host copies kept for the material and source set-up
+  std::vector<double> J;           // Jacobian (dense)
+  std::vector<double> Mface[6];    // M[xi][0..2] on face f (3 * face_n)
+  bool have_material = false;
+  int cur = 0;  // 0: state in q_a, 1: in q_b
+  double t = 0.0;
+  long long steps = 0;
+  std::vector<Src> src;
+  int width = 0;  // source stencil width 2(p+1)
+  int nrec = 0, rec_max = 0;
+  long long rec_step = 0;
+  void* rec_out = nullptr;
+  int ty = 8, zchunk = 0;
+  int nxt = 0, nyt = 0, nzc = 0;
+  bool bounds_dirty = true;
+};
+
+namespace {
+
+int check_dims(int nq, int nr, int ns, int order, int dtype) {
+  if (order != 2 && order != 4 && order != 6) return fail(SBP_EINVAL, "order must be 2, 4 or 6 (got %d)", order);
+  if (dtype != SBP_F32 && dtype != SBP_F64) return fail(SBP_EINVAL, "dtype must be SBP_F32 or SBP_F64");
+  const int mn = 2 * order;
+  if (nq < mn || nr < mn || ns < mn)
+    return fail(SBP_EINVAL, "every axis needs at least %d points for order %d (got %d x %d x %d)", mn, order, nq,
+                nr, ns);
+  if (nq > 1 << 20 || nr > 1 << 20 || ns > 1 << 20) return fail(SBP_EINVAL, "axis too long");
+  const double n = (double)nq * nr * ns;
+  if (n > 4.0e9) return fail(SBP_EINVAL, "grid too large");
+  return SBP_OK;
+}
+
+void layout(sbp_ctx* h) {
+  const int es = h->esize;
+  const Geometry& g = h->g;
+  h->px = (g.nq + 15) / 16 * 16;
+  h->plane = (std::size_t)h->px * g.nr;
+  h->field = h->plane * g.ns;
+  std::size_t o = 0;
+  auto take = [&](std::size_t bytes) {
+    std::size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  h->off_qa = take(9 * h->field * es);
+  h->off_qb = take(9 * h->field * es);
+  h->off_dq = take(9 * h->field * es);
+  h->off_coef = take(kNumCoef * h->field * es);
+  const std::size_t fn[6] = {(std::size_t)g.nr * g.ns, (std::size_t)g.nr * g.ns, (std::size_t)g.nq * g.ns,
+                             (std::size_t)g.nq * g.ns, (std::size_t)g.nq * g.nr, (std::size_t)g.nq * g.nr};
+  for (int f = 0; f < 6; ++f) {
+    h->face_n[f] = fn[f];
+    h->off_face[f] = take(kNumFaceCoef * fn[f] * es);
+  }
+  h->off_src = take((std::size_t)kMaxSources * kMaxSrcWidth * kMaxSrcWidth * kMaxSrcWidth * 6 * es);
+  h->off_rec = take((std::size_t)kMaxRec * sizeof(long long));
+  h->off_part = take(kMaxPart * sizeof(double));
+  h->off_bounds = take((std::size_t)(g.nq + g.nr + g.ns + 16) * sizeof(int));
+  h->total = o;
+}
+
+// ---- one-dimensional SBP operators on the host (double) ----------------------
+// kind 0: D+, 1: D-, 2: D0 = (D+ + D-)/2, applied along axis ax (0 q, 1 r, 2 s)
+void apply_axis(const Closure& c, const Geometry& g, const double* in, double* out, int ax, int kind) {
+  const int N = ax == 0 ? g.nq : (ax == 1 ? g.nr : g.ns);
+  const std::size_t stride = ax == 0 ? 1 : (ax == 1 ? (std::size_t)g.nq : (std::size_t)g.nq * g.nr);
+  const double ih = N - 1;
+  const int R = c.r, Q = c.q, m = c.m, nt = R + Q + 1;
+  // iterate over all lines along ax
+  const int n1 = ax == 0 ? g.nr : g.nq;
+  const int n2 = ax == 2 ? g.nr : g.ns;
+  for (int b = 0; b < n2; ++b) {
+    for (int a = 0; a < n1; ++a) {
+      std::size_t base;
+      if (ax == 0) base = g.idx(0, a, b);
+      else if (ax == 1) base = g.idx(a, 0, b);
+      else base = g.idx(a, b, 0);
+      const double* f = in + base;
+      double* o = out + base;
+      for (int i = 0; i < N; ++i) {
+        double vp = 0, vm = 0;
+        if (i >= m && i < N - m) {
+          for (int s = 0; s < nt; ++s) {
+            vp += c.alpha[s] * f[(std::size_t)(i - R + s) * stride];
+            vm -= c.alpha[s] * f[(std::size_t)(i + R - s) * stride];
+          }
+        } else if (i < m) {
+          for (int cc = 0; cc < c.ncol; ++cc) {
+            vp += c.dp[i][cc] * f[(std::size_t)cc * stride];
+            vm += c.dm[i][cc] * f[(std::size_t)cc * stride];
+          }
+        } else {
+          const int row = N - 1 - i;
+          for (int cc = 0; cc < c.ncol; ++cc) {
+            vp -= c.dm[row][cc] * f[(std::size_t)(N - 1 - cc) * stride];
+            vm -= c.dp[row][cc] * f[(std::size_t)(N - 1 - cc) * stride];
+          }
+        }
+        o[(std::size_t)i * stride] = ih * (kind == 0 ? vp : (kind == 1 ? vm : 0.5 * (vp + vm)));
+      }
+    }
+  }
+}
+
+template <typename T>
+int upload_field(sbp_ctx* h, std::size_t off, const double* src) {
+  const Geometry& g = h->g;
+  std::vector<T> tmp(g.n);
+  for (std::size_t n = 0; n < g.n; ++n) tmp[n] = (T)src[n];
+  HIPCHK(hipMemcpy2DAsync(h->ws + off, h->px * sizeof(T), tmp.data(), g.nq * sizeof(T), g.nq * sizeof(T),
+                          (std::size_t)g.nr * g.ns, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return SBP_OK;
+}
+
+int upload(sbp_ctx* h, std::size_t off, const double* src) {
+  return h->dtype == SBP_F32 ? upload_field<float>(h, off, src) : upload_field<double>(h, off, src);
+}
+
+template <typename T>
+int upload_raw(sbp_ctx* h, std::size_t off, const std::vector<double>& src) {
+  std::vector<T> tmp(src.size());
+  for (std::size_t n = 0; n < src.size(); ++n) tmp[n] = (T)src[n];
+  HIPCHK(hipMemcpyAsync(h->ws + off, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return SBP_OK;
+}
+
+int upload_vec(sbp_ctx* h, std::size_t off, const std::vector<double>& src) {
+  return h->dtype == SBP_F32 ? upload_raw<float>(h, off, src) : upload_raw<double>(h, off, src);
+}
+
+// Metric terms (Sec. 2.2): x_xi = D0_xi x, J = det, and the conservative
+// cofactor form M[xi][c] = D-_zeta(e D0_eta d) - D-_eta(e D0_zeta d) with
+// (xi, eta, zeta), (c, d, e) cyclic.  Uploads M and keeps J and face M.
+int compute_metrics(sbp_ctx* h, const double* xyz) {
+  const Geometry& g = h->g;
+  const std::size_t n = g.n;
+  std::vector<double> X(3 * n);
+  if (xyz) {
+    std::memcpy(X.data(), xyz, 3 * n * sizeof(double));
+  } else {
+    for (int k = 0; k < g.ns; ++k)
+      for (int j = 0; j < g.nr; ++j)
+        for (int i = 0; i < g.nq; ++i) {
+          const std::size_t o = g.idx(i, j, k);
+          X[o] = (double)i / (g.nq - 1);
+          X[n + o] = (double)j / (g.nr - 1);
+          X[2 * n + o] = (double)k / (g.ns - 1);
+        }
+  }
+  std::vector<double> d(9 * n);  // d[3 c + xi] = D0_xi x_c
+  for (int c = 0; c < 3; ++c)
+    for (int xi = 0; xi < 3; ++xi) apply_axis(h->cl, g, X.data() + c * n, d.data() + (3 * c + xi) * n, xi, 2);
+  h->J.assign(n, 0.0);
+  for (std::size_t o = 0; o < n; ++o) {
+    const double xq = d[0 * n + o], xr = d[1 * n + o], xs = d[2 * n + o];
+    const double yq = d[3 * n + o], yr = d[4 * n + o], ys = d[5 * n + o];
+    const double zq = d[6 * n + o], zr = d[7 * n + o], zs = d[8 * n + o];
+    const double J = xq * (yr * zs - zr * ys) - yq * (xr * zs - zr * xs) + zq * (xr * ys - yr * xs);
+    if (!(J > 0)) return fail(SBP_EINVAL, "non-positive Jacobian at node %zu", o);
+    h->J[o] = J;
+  }
+  std::vector<double> tmp(n), t1(n), t2(n);
+  for (int xi = 0; xi < 3; ++xi) {
+    const int eta = (xi + 1) % 3, zeta = (xi + 2) % 3;
+    for (int c = 0; c < 3; ++c) {
+      const int dd = (c + 1) % 3, e = (c + 2) % 3;
+      for (std::size_t o = 0; o < n; ++o) tmp[o] = X[e * n + o] * d[(3 * dd + eta) * n + o];
+      apply_axis(h->cl, g, tmp.data(), t1.data(), zeta, 1);
+      for (std::size_t o = 0; o < n; ++o) tmp[o] = X[e * n + o] * d[(3 * dd + zeta) * n + o];
+      apply_axis(h->cl, g, tmp.data(), t2.data(), eta, 1);
+      for (std::size_t o = 0; o < n; ++o) t1[o] -= t2[o];
+      int rc = upload(h, h->off_coef + (std::size_t)(3 * xi + c) * h->field * h->esize, t1.data());
+      if (rc) return rc;
+      // keep the face values of M[xi][.] for the penalties of faces 2 xi, 2 xi + 1
+      for (int side = 0; side < 2; ++side) {
+        const int f = 2 * xi + side;
+        auto& Mf = h->Mface[f];
+        if (Mf.empty()) Mf.assign(3 * h->face_n[f], 0.0);
+        std::size_t a = 0;
+        if (xi == 0) {
+          const int i = side ? g.nq - 1 : 0;
+          for (int k = 0; k < g.ns; ++k)
+            for (int j = 0; j < g.nr; ++j) Mf[c * h->face_n[f] + a++] = t1[g.idx(i, j, k)];
+        } else if (xi == 1) {
+          const int j = side ? g.nr - 1 : 0;
+          for (int k = 0; k < g.ns; ++k)
+            for (int i = 0; i < g.nq; ++i) Mf[c * h->face_n[f] + a++] = t1[g.idx(i, j, k)];
+        } else {
+          const int k = side ? g.ns - 1 : 0;
+          for (int j = 0; j < g.nr; ++j)
+            for (int i = 0; i < g.nq; ++i) Mf[c * h->face_n[f] + a++] = t1[g.idx(i, j, k)];
+        }
+      }
+    }
+  }
+  return SBP_OK;
+}
+
+// balanced split of [0, N) into tiles of width <= W whose first and last tile
+// hold at least m points (so SBP closure rows never straddle a tile edge)
+std::vector<int> tile_bounds(int N, int W, int m) {
+  std::vector<int> b;
+  if (N <= W) return {0, N};
+  int T = (N + W - 1) / W;
+  for (int t = 0; t <= T; ++t) b.push_back((int)((long long)t * N / T));
+  if (b[1] - b[0] >= m && b[T] - b[T - 1] >= m) return b;
+  // fall back: full first and last tiles, balanced middle
+  b.assign(1, 0);
+  b.push_back(W);
+  const int mid = N - 2 * W;
+  if (mid > 0) {
+    const int Tm = (mid + W - 1) / W;
+    for (int t = 1; t <= Tm; ++t) b.push_back(W + (int)((long long)t * mid / Tm));
+  }
+  if (b.back() != N - W) b.push_back(N - W);
+  b.push_back(N);
+  return b;
+}
+
+int prepare_bounds(sbp_ctx* h) {
+  if (!h->bounds_dirty) return SBP_OK;
+  const Geometry& g = h->g;
+  std::vector<int> xb = tile_bounds(g.nq, 64, h->cl.m);
+  std::vector<int> yb = tile_bounds(g.nr, h->ty, h->cl.m);
+  h->nxt = (int)xb.size() - 1;
+  h->nyt = (int)yb.size() - 1;
+  int zc = h->zchunk;
+  if (zc <= 0) {
+    // aim at >= 8 resident blocks per compute unit on 256 CUs
+    const long long want = 2048;
+    const long long cols = (long long)h->nxt * h->nyt;
+    long long nz = (want + cols - 1) / cols;
+    nz = std::max(1LL, std::min(nz, (long long)g.ns / 16 > 0 ? (long long)g.ns / 16 : 1LL));
+    zc = (int)((g.ns + nz - 1) / nz);
+  }
+  zc = std::max(1, std::min(zc, g.ns));
+  h->nzc = (g.ns + zc - 1) / zc;
+  std::vector<int> all(xb);
+  all.insert(all.end(), yb.begin(), yb.end());
+  for (int t = 0; t <= h->nzc; ++t) all.push_back((int)((long long)t * g.ns / h->nzc));
+  HIPCHK(hipMemcpyAsync(h->ws + h->off_bounds, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice,
+                        h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->bounds_dirty = false;
+  return SBP_OK;
+}
+
+double stf_value(const Src& s, double t) {
+  if (s.stf == SBP_STF_RICKER) {
+    const double a = kPi * s.param * (t - s.t0);
+    const double a2 = a * a;
+    return (1.0 - 2.0 * a2) * std::exp(-a2);
+  }
+  const double tt = t - s.t0;
+  return tt >= 0 ? tt / (s.param * s.param) * std::exp(-tt / s.param) : 0.0;
+}
+
+template <typename T>
+StageArgs<T> stage_args(sbp_ctx* h) {
+  StageArgs<T> a{};
+  const Geometry& g = h->g;
+  a.coef = (const T*)(h->ws + h->off_coef);
+  a.face = (const T*)h->ws;
+  for (int f = 0; f < 6; ++f) {
+    a.face_off[f] = h->off_face[f] / sizeof(T);
+    a.face_n[f] = h->face_n[f];
+    a.gamma[f] = (T)h->gamma[f];
+    a.traction[f] = (h->sat_variant == SBP_SAT_TRACTION && h->gamma[f] == 1.0) ? 1 : 0;
+  }
+  a.bounds = (const int*)(h->ws + h->off_bounds);
+  a.plane = h->plane;
+  a.field = h->field;
+  a.px = h->px;
+  a.nq = g.nq;
+  a.nr = g.nr;
+  a.ns = g.ns;
+  a.nxt = h->nxt;
+  a.nyt = h->nyt;
+  a.nzc = h->nzc;
+  a.ntiles = h->nxt * h->nyt * h->nzc;
+  a.ncol = h->cl.ncol;
+  a.inv_h[0] = (T)(g.nq - 1);
+  a.inv_h[1] = (T)(g.nr - 1);
+  a.inv_h[2] = (T)(g.ns - 1);
+  for (int i = 0; i < kMaxM; ++i)
+    for (int c = 0; c < kMaxCols; ++c) {
+      a.dp[i][c] = (T)h->cl.dp[i][c];
+      a.dm[i][c] = (T)h->cl.dm[i][c];
+    }
+  return a;
+}
+
+template <typename T>
+int run_stage(sbp_ctx* h, StageArgs<T>& a, int k, double dt, double tstage, bool rhs_only, T* qin, T* qout) {
+  T* dq = (T*)(h->ws + h->off_dq);
+  a.qin = qin;
+  a.qout = qout;
+  a.dq = dq;
+  a.read_dq = (!rhs_only && k > 0) ? 1 : 0;
+  a.Ak = rhs_only ? T(0) : (T)kRkA[k];
+  a.Bk = rhs_only ? T(0) : (T)kRkB[k];
+  a.dt = rhs_only ? T(1) : (T)dt;
+  HIPCHK(launch_stage<T>(h->order, h->ty, a, h->stream));
+  if (!h->src.empty()) {
+    SourceArgs<T> s{};
+    s.dq = dq;
+    s.qout = rhs_only ? nullptr : qout;
+    s.wm = (const T*)(h->ws + h->off_src);
+    s.plane = h->plane;
+    s.field = h->field;
+    s.px = h->px;
+    s.width = h->width;
+    s.Bk = rhs_only ? T(0) : (T)kRkB[k];
+    for (std::size_t i = 0; i < h->src.size(); ++i) {
+      s.i0[i] = h->src[i].i0;
+      s.j0[i] = h->src[i].j0;
+      s.k0[i] = h->src[i].k0;
+      s.gdt[i] = (T)((rhs_only ? 1.0 : dt) * stf_value(h->src[i], tstage));
+    }
+    HIPCHK(launch_source<T>(s, (int)h->src.size(), h->stream));
+  }
+  return SBP_OK;
+}
+
+template <typename T>
+int do_steps(sbp_ctx* h, int nsteps, double dt) {
+  int rc = prepare_bounds(h);
+  if (rc) return rc;
+  StageArgs<T> a = stage_args<T>(h);
+  T* qa = (T*)(h->ws + h->off_qa);
+  T* qb = (T*)(h->ws + h->off_qb);
+  const double t0 = h->t;
+  for (int n = 0; n < nsteps; ++n) {
+    const double tn = t0 + n * dt;
+    for (int k = 0; k < 5; ++k) {
+      T* qin = h->cur ? qb : qa;
+      T* qout = h->cur ? qa : qb;
+      rc = run_stage<T>(h, a, k, dt, tn + kRkC[k] * dt, false, qin, qout);
+      if (rc) return rc;
+      h->cur ^= 1;
+    }
+    if (h->nrec > 0) {
+      T* q = h->cur ? qb : qa;
+      T* out = (T*)h->rec_out + (std::size_t)h->rec_step * h->nrec * 3;
+      HIPCHK(launch_record<T>(q, h->field, (const long long*)(h->ws + h->off_rec), h->nrec, out, h->stream));
+      ++h->rec_step;
+    }
+    ++h->steps;
+  }
+  h->t = t0 + nsteps * dt;
+  return SBP_OK;
+}
+
+template <typename T>
+int do_rhs(sbp_ctx* h, void* out, double t) {
+  int rc = prepare_bounds(h);
+  if (rc) return rc;
+  StageArgs<T> a = stage_args<T>(h);
+  T* qa = (T*)(h->ws + h->off_qa);
+  T* qb = (T*)(h->ws + h->off_qb);
+  T* qin = h->cur ? qb : qa;
+  T* qout = h->cur ? qa : qb;
+  rc = run_stage<T>(h, a, 0, 1.0, t, true, qin, qout);
+  if (rc) return rc;
+  const Geometry& g = h->g;
+  HIPCHK(hipMemcpy2DAsync(out, g.nq * sizeof(T), h->ws + h->off_dq, h->px * sizeof(T), g.nq * sizeof(T),
+                          (std::size_t)9 * g.nr * g.ns, hipMemcpyDeviceToDevice, h->stream));
+  return SBP_OK;
+}
+
+template <typename T>
+int do_energy(sbp_ctx* h, double* E) {
+  EnergyArgs<T> e{};
+  const Geometry& g = h->g;
+  e.q = (const T*)(h->ws + (h->cur ? h->off_qb : h->off_qa));
+  e.coef = (const T*)(h->ws + h->off_coef);
+  e.part = (double*)(h->ws + h->off_part);
+  e.plane = h->plane;
+  e.field = h->field;
+  e.px = h->px;
+  e.nq = g.nq;
+  e.nr = g.nr;
+  e.ns = g.ns;
+  e.m = h->cl.m;
+  e.h[0] = 1.0 / (g.nq - 1);
+  e.h[1] = 1.0 / (g.nr - 1);
+  e.h[2] = 1.0 / (g.ns - 1);
+  for (int i = 0; i < kMaxM; ++i) e.w[i] = h->cl.w[i];
+  const int nb = (int)std::min<std::size_t>(kMaxPart, (g.n + 255) / 256);
+  HIPCHK(launch_energy<T>(e, nb, h->stream));
+  std::vector<double> part(nb);
+  HIPCHK(hipMemcpyAsync(part.data(), e.part, nb * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  double s = 0;
+  for (double v : part) s += v;
+  *E = s;
+  if (!std::isfinite(s)) return fail(SBP_EUNSTABLE, "energy is not finite");
+  return SBP_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+extern "C" {
+
+const char* sbp_last_error(void) { return g_err.c_str(); }
+
+int sbp_workspace_bytes(int nq, int nr, int ns, int order, int dtype, size_t* bytes) {
+  if (!bytes) return fail(SBP_EINVAL, "bytes is NULL");
+  int rc = check_dims(nq, nr, ns, order, dtype);
+  if (rc) return rc;
+  sbp_ctx tmp;
+  tmp.esize = dtype == SBP_F32 ? 4 : 8;
+  tmp.g = Geometry{nq, nr, ns, (std::size_t)nq * nr * ns};
+  layout(&tmp);
+  *bytes = tmp.total;
+  return SBP_OK;
+}
+
+int sbp_init_grid(sbp_handle* out, int nq, int nr, int ns, const double* xyz, int order, int dtype,
+                  const double* gamma, int sat_variant, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!out) return fail(SBP_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = check_dims(nq, nr, ns, order, dtype);
+  if (rc) return rc;
+  if (!gamma) return fail(SBP_EINVAL, "gamma is NULL");
+  for (int f = 0; f < 6; ++f)
+    if (!(gamma[f] >= -1.0 && gamma[f] <= 1.0)) return fail(SBP_EINVAL, "gamma[%d] = %g outside [-1, 1]", f, gamma[f]);
+  if (sat_variant != SBP_SAT_CHARACTERISTIC && sat_variant != SBP_SAT_TRACTION)
+    return fail(SBP_EINVAL, "unknown sat_variant %d", sat_variant);
+  if (!workspace) return fail(SBP_EINVAL, "workspace is NULL");
+  if ((reinterpret_cast<std::uintptr_t>(workspace) & 255) != 0) return fail(SBP_EINVAL, "workspace not 256-byte aligned");
+  sbp_ctx* h = new sbp_ctx();
+  h->order = order;
+  h->dtype = dtype;
+  h->esize = dtype == SBP_F32 ? 4 : 8;
+  h->g = Geometry{nq, nr, ns, (std::size_t)nq * nr * ns};
+  for (int f = 0; f < 6; ++f) h->gamma[f] = gamma[f];
+  h->sat_variant = sat_variant;
+  h->stream = (hipStream_t)stream;
+  h->ws = (char*)workspace;
+  h->ws_bytes = workspace_bytes;
+  h->width = 2 * (order / 2 + 1);
+  layout(h);
+  if (workspace_bytes < h->total) {
+    std::size_t need = h->total;
+    delete h;
+    return fail(SBP_ENOMEM, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
+  }
+  const char* err = "";
+  if (!build_closure(order, &h->cl, &err)) {
+    delete h;
+    return fail(SBP_EINVAL, "closure construction failed: %s", err);
+  }
+  // zero the state buffers and the Runge-Kutta register
+  hipError_t e = hipMemsetAsync(h->ws, 0, h->off_coef, h->stream);
+  if (e != hipSuccess) {
+    delete h;
+    return fail(SBP_EHIP, "hipMemsetAsync: %s", hipGetErrorString(e));
+  }
+  rc = compute_metrics(h, xyz);
+  if (rc) {
+    std::string keep = g_err;
+    delete h;
+    g_err = keep;
+    return rc;
+  }
+  *out = h;
+  return SBP_OK;
+}
+
+int sbp_set_material(sbp_handle h, const double* rho, const double* cp, const double* cs) {
+  if (!h || !rho || !cp || !cs) return fail(SBP_EINVAL, "NULL argument");
+  const Geometry& g = h->g;
+  const std::size_t n = g.n;
+  std::vector<double> lamJ(n), muJ(n), rJ(n);
+  for (std::size_t o = 0; o < n; ++o) {
+    const double mu = rho[o] * cs[o] * cs[o];
+    const double lam = rho[o] * cp[o] * cp[o] - 2.0 * mu;
+    if (!(rho[o] > 0) || !(mu > 0) || !(3 * lam + 2 * mu > 0))
+      return fail(SBP_EINVAL, "material not positive definite at node %zu", o);
+    lamJ[o] = lam / h->J[o];
+    muJ[o] = mu / h->J[o];
+    rJ[o] = 1.0 / (rho[o] * h->J[o]);
+  }
+  int rc;
+  if ((rc = upload(h, h->off_coef + 9 * h->field * h->esize, lamJ.data()))) return rc;
+  if ((rc = upload(h, h->off_coef + 10 * h->field * h->esize, muJ.data()))) return rc;
+  if ((rc = upload(h, h->off_coef + 11 * h->field * h->esize, rJ.data()))) return rc;
+  // face penalty coefficients
+  for (int f = 0; f < 6; ++f) {
+    const int xi = f / 2, side = f % 2;
+    const std::size_t fn = h->face_n[f];
+    const int N = xi == 0 ? g.nq : (xi == 1 ? g.nr : g.ns);
+    const double hw0 = h->cl.w[0] / (N - 1);
+    std::vector<double> fc(kNumFaceCoef * fn);
+    std::size_t a = 0;
+    auto node = [&](std::size_t idx) {
+      const double M0 = h->Mface[f][idx], M1 = h->Mface[f][fn + idx], M2 = h->Mface[f][2 * fn + idx];
+      std::size_t o;
+      if (xi == 0) o = g.idx(side ? g.nq - 1 : 0, (int)(idx % g.nr), (int)(idx / g.nr));
+      else if (xi == 1) o = g.idx((int)(idx % g.nq), side ? g.nr - 1 : 0, (int)(idx / g.nq));
+      else o = g.idx((int)(idx % g.nq), (int)(idx / g.nq), side ? g.ns - 1 : 0);
+      const double nrm = std::sqrt(M0 * M0 + M1 * M1 + M2 * M2);
+      const double kappa = nrm / (h->J[o] * hw0);
+      const double mu = rho[o] * cs[o] * cs[o];
+      const double lam = rho[o] * cp[o] * cp[o] - 2.0 * mu;
+      const double zp = rho[o] * cp[o], zs = rho[o] * cs[o];
+      fc[FN_X * fn + idx] = M0 / nrm;
+      fc[FN_Y * fn + idx] = M1 / nrm;
+      fc[FN_Z * fn + idx] = M2 / nrm;
+      fc[F_ZP * fn + idx] = zp;
+      fc[F_ZS * fn + idx] = zs;
+      fc[F_IZP * fn + idx] = 1.0 / zp;
+      fc[F_IZS * fn + idx] = 1.0 / zs;
+      fc[F_KR * fn + idx] = kappa / rho[o];
+      fc[F_KL * fn + idx] = kappa * lam;
+      fc[F_KM * fn + idx] = kappa * mu;
+    };
+    for (a = 0; a < fn; ++a) node(a);
+    if ((rc = upload_vec(h, h->off_face[f], fc))) return rc;
+  }
+  h->have_material = true;
+  return SBP_OK;
+}
+
+int sbp_add_source(sbp_handle h, const double* xi, const double* M, int stf, double param, double t0) {
+  if (!h || !xi || !M) return fail(SBP_EINVAL, "NULL argument");
+  if ((int)h->src.size() >= kMaxSources) return fail(SBP_EINVAL, "at most %d sources", kMaxSources);
+  if (stf != SBP_STF_RICKER && stf != SBP_STF_EXPT) return fail(SBP_EINVAL, "unknown source-time function");
+  if (!(param > 0)) return fail(SBP_EINVAL, "source parameter must be positive");
+  for (int a = 0; a < 3; ++a)
+    if (!(xi[a] >= 0.0 && xi[a] <= 1.0)) return fail(SBP_EINVAL, "source outside the block");
+  const Geometry& g = h->g;
+  const int w = h->width;
+  const int Ns[3] = {g.nq, g.nr, g.ns};
+  int start[3];
+  double d[3][kMaxSrcWidth];
+  for (int ax = 0; ax < 3; ++ax) {
+    const int N = Ns[ax];
+    const double u = xi[ax] * (N - 1);
+    int s0 = (int)std::floor(u) - w / 2 + 1;
+    s0 = std::min(std::max(s0, 0), N - w);
+    start[ax] = s0;
+    for (int a = 0; a < w; ++a) {
+      double num = 1, den = 1;
+      for (int b = 0; b < w; ++b)
+        if (b != a) {
+          num *= u - (s0 + b);
+          den *= (double)(a - b);
+        }
+      const int node = s0 + a;
+      double Hw = 1.0;
+      if (node < h->cl.m) Hw = h->cl.w[node];
+      else if (node >= N - h->cl.m) Hw = h->cl.w[N - 1 - node];
+      d[ax][a] = (num / den) / (Hw / (N - 1));
+    }
+  }
+  const std::size_t per = (std::size_t)kMaxSrcWidth * kMaxSrcWidth * kMaxSrcWidth * 6;
+  std::vector<double> wm(per, 0.0);
+  for (int c = 0; c < w; ++c)
+    for (int b = 0; b < w; ++b)
+      for (int a = 0; a < w; ++a) {
+        const int t = (c * w + b) * w + a;
+        const double wt = d[0][a] * d[1][b] * d[2][c] / h->J[g.idx(start[0] + a, start[1] + b, start[2] + c)];
+        for (int f = 0; f < 6; ++f) wm[(std::size_t)t * 6 + f] = wt * M[f];
+      }
+  const std::size_t off = h->off_src + h->src.size() * per * h->esize;
+  int rc = upload_vec(h, off, wm);
+  if (rc) return rc;
+  Src s;
+  s.i0 = start[0];
+  s.j0 = start[1];
+  s.k0 = start[2];
+  for (int f = 0; f < 6; ++f) s.M[f] = M[f];
+  s.stf = stf;
+  s.param = param;
+  s.t0 = t0;
+  h->src.push_back(s);
+  return SBP_OK;
+}
+
+int sbp_clear_sources(sbp_handle h) {
+  if (!h) return fail(SBP_EINVAL, "NULL handle");
+  h->src.clear();
+  return SBP_OK;
+}
+
+int sbp_set_state(sbp_handle h, const void* q, int q_is_device, double t) {
+  if (!h || !q) return fail(SBP_EINVAL, "NULL argument");
+  const Geometry& g = h->g;
+  const std::size_t es = h->esize;
+  char* dst = h->ws + (h->cur ? h->off_qb : h->off_qa);
+  HIPCHK(hipMemcpy2DAsync(dst, h->px * es, q, g.nq * es, g.nq * es, (std::size_t)9 * g.nr * g.ns,
+                          q_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
+  if (!q_is_device) HIPCHK(hipStreamSynchronize(h->stream));
+  h->t = t;
+  return SBP_OK;
+}
+
+int sbp_get_state(sbp_handle h, void* q, int q_is_device, double* t_out) {
+  if (!h || !q) return fail(SBP_EINVAL, "NULL argument");
+  const Geometry& g = h->g;
+  const std::size_t es = h->esize;
+  const char* src = h->ws + (h->cur ? h->off_qb : h->off_qa);
+  HIPCHK(hipMemcpy2DAsync(q, g.nq * es, src, h->px * es, g.nq * es, (std::size_t)9 * g.nr * g.ns,
+                          q_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+  if (!q_is_device) HIPCHK(hipStreamSynchronize(h->stream));
+  if (t_out) *t_out = h->t;
+  return SBP_OK;
+}
+
+int sbp_record(sbp_handle h, int nrec, const int* ijk, void* out_device, int max_steps) {
+  if (!h) return fail(SBP_EINVAL, "NULL handle");
+  if (nrec < 0 || nrec > kMaxRec) return fail(SBP_EINVAL, "nrec must be in [0, %d]", kMaxRec);
+  if (nrec == 0) {
+    h->nrec = 0;
+    return SBP_OK;
+  }
+  if (!ijk || !out_device || max_steps <= 0) return fail(SBP_EINVAL, "invalid receiver arguments");
+  const Geometry& g = h->g;
+  std::vector<long long> off(nrec);
+  for (int r = 0; r < nrec; ++r) {
+    const int i = ijk[3 * r], j = ijk[3 * r + 1], k = ijk[3 * r + 2];
+    if (i < 0 || i >= g.nq || j < 0 || j >= g.nr || k < 0 || k >= g.ns)
+      return fail(SBP_EINVAL, "receiver %d outside the grid", r);
+    off[r] = (long long)k * h->plane + (long long)j * h->px + i;
+  }
+  HIPCHK(hipMemcpyAsync(h->ws + h->off_rec, off.data(), nrec * sizeof(long long), hipMemcpyHostToDevice,
+                        h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->nrec = nrec;
+  h->rec_out = out_device;
+  h->rec_max = max_steps;
+  h->rec_step = 0;
+  return SBP_OK;
+}
+
+int sbp_step(sbp_handle h, int nsteps, double dt) {
+  if (!h) return fail(SBP_EINVAL, "NULL handle");
+  if (!h->have_material) return fail(SBP_ESTATE, "sbp_set_material has not been called");
+  if (nsteps < 0 || !(dt > 0) || !std::isfinite(dt)) return fail(SBP_EINVAL, "need nsteps >= 0 and dt > 0");
+  if (h->nrec > 0 && h->rec_step + nsteps > h->rec_max)
+    return fail(SBP_EINVAL, "receiver buffer holds %d steps; %lld recorded, %d requested", h->rec_max,
+                h->rec_step, nsteps);
+  return h->dtype == SBP_F32 ? do_steps<float>(h, nsteps, dt) : do_steps<double>(h, nsteps, dt);
+}
+
+int sbp_rhs(sbp_handle h, void* out_device, double t) {
+  if (!h || !out_device) return fail(SBP_EINVAL, "NULL argument");
+  if (!h->have_material) return fail(SBP_ESTATE, "sbp_set_material has not been called");
+  return h->dtype == SBP_F32 ? do_rhs<float>(h, out_device, t) : do_rhs<double>(h, out_device, t);
+}
+
+int sbp_energy(sbp_handle h, double* E) {
+  if (!h || !E) return fail(SBP_EINVAL, "NULL argument");
+  if (!h->have_material) return fail(SBP_ESTATE, "sbp_set_material has not been called");
+  return h->dtype == SBP_F32 ? do_energy<float>(h, E) : do_energy<double>(h, E);
+}
+
+int sbp_set_launch(sbp_handle h, int ty, int zchunk) {
+  if (!h) return fail(SBP_EINVAL, "NULL handle");
+  if (ty != 4 && ty != 8) return fail(SBP_EINVAL, "ty must be 4 or 8");
+  if (ty < h->cl.m) return fail(SBP_EINVAL, "ty must be >= %d for order %d", h->cl.m, h->order);
+  if (zchunk < 0) return fail(SBP_EINVAL, "zchunk must be >= 0");
+  h->ty = ty;
+  h->zchunk = zchunk;
+  h->bounds_dirty = true;
+  return SBP_OK;
+}
+
+int sbp_time(sbp_handle h, double* t, long long* steps) {
+  if (!h) return fail(SBP_EINVAL, "NULL handle");
+  if (t) *t = h->t;
+  if (steps) *steps = h->steps;
+  return SBP_OK;
+}
+
+int sbp_destroy(sbp_handle h) {
+  delete h;
+  return SBP_OK;
+}
+
+}  // extern "C"

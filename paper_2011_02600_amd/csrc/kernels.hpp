@@ -1,0 +1,68 @@
+// Kernel argument blocks and launchers (host <-> device interface).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "internal.hpp"
+
+namespace sbp {
+
+template <typename T>
+struct StageArgs {
+  const T* qin;       // 9 fields, current stage input
+  T* qout;            // 9 fields, stage output
+  T* dq;              // 9 fields, Runge-Kutta register (read if read_dq)
+  const T* coef;      // 12 fields: M[xi][c] (3 xi + c), lambda/J, mu/J, 1/(rho J)
+  const T* face;      // workspace base for the face coefficient arrays
+  const int* bounds;  // tile bounds: q (nxt+1), r (nyt+1), s (nzc+1)
+  std::size_t face_off[6];
+  std::size_t face_n[6];
+  std::size_t plane, field;
+  int px, nq, nr, ns;
+  int nxt, nyt, nzc, ntiles;
+  int ncol;
+  int read_dq;
+  int traction[6];
+  T Ak, Bk, dt;
+  T inv_h[3];
+  T gamma[6];
+  T dp[kMaxM][kMaxCols];  // closure rows of h D+ (left end)
+  T dm[kMaxM][kMaxCols];  // closure rows of h D- (left end)
+};
+
+template <typename T>
+struct SourceArgs {
+  T* dq;
+  T* qout;       // may be null (RHS evaluation only)
+  const T* wm;   // per source: width^3 nodes x 6 weights (w * M_c), padded to kMaxSrcWidth^3
+  std::size_t plane, field;
+  int px, width;
+  int i0[kMaxSources], j0[kMaxSources], k0[kMaxSources];
+  T gdt[kMaxSources];  // dt * g(t_stage) per source
+  T Bk;
+};
+
+template <typename T>
+struct EnergyArgs {
+  const T* q;
+  const T* coef;
+  double* part;
+  std::size_t plane, field;
+  int px, nq, nr, ns, m;
+  double h[3];
+  double w[kMaxM];
+};
+
+template <typename T>
+hipError_t launch_stage(int order, int ty, const StageArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_source(const SourceArgs<T>& s, int nsrc, hipStream_t st);
+template <typename T>
+hipError_t launch_record(const T* q, std::size_t field, const long long* off, int nrec, T* out,
+                         hipStream_t st);
+template <typename T>
+hipError_t launch_energy(const EnergyArgs<T>& e, int nblocks, hipStream_t st);
+
+}  // namespace sbp

@@ -1,0 +1,276 @@
+"""GPU parity: the HIP library (called through its C ABI) against the CPU
+oracle on the same seeded inputs.
+
+Bars: relative L2 error per field <= 1e-12 in FP64 and <= 2e-5 in FP32 after
+100 steps; single right-hand-side evaluations are compared field by field
+relative to the field's largest value.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import elastic as E
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-12, "f32": 2e-5}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def sbp_mod():
+    from paper_2011_02600_amd import sbp
+    return sbp
+
+
+def rel_l2(got, want):
+    errs = []
+    for f in range(want.shape[0]):
+        nw = np.linalg.norm(want[f])
+        ne = np.linalg.norm(got[f] - want[f])
+        errs.append(ne / nw if nw > 0 else ne)
+    return max(errs)
+
+
+def rel_max(got, want):
+    errs = []
+    for f in range(want.shape[0]):
+        nw = np.abs(want[f]).max()
+        ne = np.abs(got[f] - want[f]).max()
+        errs.append(ne / nw if nw > 0 else ne)
+    return max(errs)
+
+
+def make_solver(xyz, order, dtype, gamma, variant=0, medium=None):
+    sbp = sbp_mod()
+    s = sbp.Solver(xyz, order=order, dtype=dtype, gamma=gamma, sat_variant=variant)
+    if medium is not None:
+        s.set_material(*medium)
+    return s
+
+
+def test_cube_pulse_fp64_100_steps():
+    """Cartesian unit cube 21^3, order 4, FP64, free surface on top and
+    absorbing elsewhere, Gaussian pulse, CFL 0.5, 100 steps."""
+    say("case: cube_pulse 21^3 order 4 f64 100 steps")
+    wl = W.cube_pulse(n=21)
+    s = make_solver(wl["xyz"], 4, "f64", wl["gamma"], medium=(wl["rho"], wl["cp"], wl["cs"]))
+    s.set_state(wl["Q0"])
+    e0 = s.energy()
+    s.step(100, wl["dt"])
+    got = s.get_state().cpu().numpy()
+    e1 = s.energy()
+    blk = E.Block(wl["xyz"], 4).set_material(wl["rho"], wl["cp"], wl["cs"])
+    want, t, _ = E.run(blk, wl["Q0"], 100, wl["dt"], wl["gamma"])
+    err = rel_l2(got, want)
+    say("  rel L2 = %.3e" % err)
+    assert err <= TOL["f64"]
+    assert abs(e0 - E.energy(blk, wl["Q0"])) <= 1e-12 * e0
+    assert abs(e1 - E.energy(blk, want)) <= 1e-12 * e0
+    assert e1 < e0
+    assert abs(s.time()[0] - 100 * wl["dt"]) < 1e-12
+    s.close()
+
+
+RHS_CASES = [
+    # order, (ns, nr, nq), dtype, variant
+    (2, (4, 4, 4), "f64", 0),
+    (4, (8, 8, 8), "f64", 1),
+    (6, (12, 12, 12), "f64", 0),
+    (2, (11, 9, 70), "f64", 1),
+    (4, (19, 23, 70), "f64", 0),
+    (4, (19, 23, 70), "f32", 1),
+    (6, (17, 13, 131), "f64", 0),
+    (6, (17, 13, 131), "f32", 0),
+    (6, (25, 21, 17), "f64", 1),
+    (6, (13, 30, 65), "f32", 1),
+]
+
+
+@pytest.mark.parametrize("order,shape,dtype,variant", RHS_CASES)
+def test_rhs_parity(order, shape, dtype, variant):
+    """One right-hand-side evaluation (volume terms, penalties on all six
+    faces with mixed gamma, one source) on a warped mesh with a random medium.
+    Shapes span several tiles with ragged tails and include the minimum size
+    (2 m points per axis)."""
+    say("case: rhs order %d shape %s %s variant %d" % (order, shape, dtype, variant))
+    ns, nr, nq = shape
+    xyz = W.warped_mesh(nq, nr, ns, seed=order + nq)
+    med = W.random_medium(shape, 3)
+    gamma = [1.0, 0.0, -1.0, 0.4, 0.0, 1.0]
+    Q = W.random_state(shape, 5, smooth=(dtype == "f32"))
+    s = make_solver(xyz, order, dtype, gamma, variant, med)
+    Msrc = (0.3, -0.1, 0.2, 1.0, -0.5, 0.25)
+    xi = (0.37, 0.52, 0.61)
+    s.add_source(xi, Msrc, 0, 2.0, 0.1)
+    s.set_state(Q)
+    t = 0.13
+    got = s.rhs(t).cpu().numpy().astype(np.float64)
+    blk = E.Block(xyz, order).set_material(*med)
+    src = E.Source(blk, xi, Msrc, E.STF_RICKER, 2.0, 0.1)
+    want = E.rhs(blk, Q, t, gamma, variant, [src])
+    err = rel_max(got, want)
+    say("  rel max = %.3e" % err)
+    assert err <= (1e-12 if dtype == "f64" else 1e-5)
+    # the state is untouched by an RHS evaluation
+    back = s.get_state().cpu().numpy()
+    assert np.array_equal(back, Q.astype(back.dtype))
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_topo_layer_small_100_steps(dtype):
+    """The curvilinear layered workload (topography, transfinite mesh, soft
+    layer over a half-space, Ricker moment source, surface receivers) at a
+    reduced size: 100 steps, state and receiver traces against the oracle."""
+    say("case: topo_layer 49x45x37 order 6 %s 100 steps" % dtype)
+    wl = W.topo_layer(nq=49, nr=45, ns=37, nrec_side=4)
+    s = make_solver(wl["xyz"], 6, dtype, wl["gamma"], medium=(wl["rho"], wl["cp"], wl["cs"]))
+    s.add_source(wl["src_xi"], wl["src_M"], 0, wl["src_f0"], wl["src_t0"])
+    traces = s.record(wl["receivers"], 100)
+    s.step(100, wl["dt"])
+    got = s.get_state().cpu().numpy().astype(np.float64)
+    tr = traces.cpu().numpy().astype(np.float64)
+    blk = E.Block(wl["xyz"], 6).set_material(wl["rho"], wl["cp"], wl["cs"])
+    src = E.Source(blk, wl["src_xi"], wl["src_M"], E.STF_RICKER, wl["src_f0"], wl["src_t0"])
+    want, _, wtr = E.run(blk, wl["Q0"], 100, wl["dt"], wl["gamma"], sources=[src], receivers=wl["receivers"])
+    err = rel_l2(got, want)
+    terr = np.linalg.norm(tr - wtr) / np.linalg.norm(wtr)
+    say("  state rel L2 = %.3e, traces rel L2 = %.3e" % (err, terr))
+    assert err <= TOL[dtype]
+    assert terr <= TOL[dtype]
+    s.close()
+
+
+def test_full_size_sampled_rhs():
+    """The 257 x 257 x 193 order-6 FP32 workload in the benchmark's launch
+    configuration: the GPU right-hand side against the oracle evaluated node by
+    node at sampled nodes (interior, closure planes, faces, edges, corners and
+    the source support)."""
+    say("case: full-size 257x257x193 order 6 f32 sampled rhs")
+    wl = W.topo_layer()
+    ns, nr, nq = wl["xyz"].shape[1:]
+    Q = W.random_state((ns, nr, nq), 21, smooth=True)
+    s = make_solver(wl["xyz"], 6, "f32", wl["gamma"], medium=(wl["rho"], wl["cp"], wl["cs"]))
+    s.add_source(wl["src_xi"], wl["src_M"], 0, wl["src_f0"], wl["src_t0"])
+    s.set_state(Q)
+    t = 0.5
+    got = s.rhs(t).cpu().numpy()
+    s.close()
+    blk = E.Block(wl["xyz"], 6).set_material(wl["rho"], wl["cp"], wl["cs"])
+    src = E.Source(blk, wl["src_xi"], wl["src_M"], E.STF_RICKER, wl["src_f0"], wl["src_t0"])
+    rng = np.random.default_rng(0)
+    nodes = [tuple(int(rng.integers(0, n)) for n in (nq, nr, ns)) for _ in range(150)]
+    for i in (0, 1, 5, 6, 7, nq // 2, nq - 7, nq - 6, nq - 1):
+        for k in (0, 3, 5, 6, ns // 2, ns - 6, ns - 1):
+            nodes.append((i, int(rng.integers(0, nr)), k))
+    nodes += [(0, 0, 0), (nq - 1, nr - 1, ns - 1), (0, nr - 1, ns - 1), (nq - 1, 0, 0)]
+    ks, js, is_ = src.sl
+    nodes += [(is_.start + 3, js.start + 4, ks.start + 2), (is_.start, js.start, ks.start)]
+    want = E.rhs_at(blk, Q, nodes, t, wl["gamma"], sources=[src])
+    g = np.array([got[:, k, j, i] for i, j, k in nodes], dtype=np.float64)
+    scale = np.abs(want).max(axis=0)
+    err = (np.abs(g - want).max(axis=0) / scale).max()
+    say("  sampled rel max = %.3e over %d nodes" % (err, len(nodes)))
+    assert err <= 1e-5
+
+
+def test_full_size_energy_decreases():
+    """Property at full size: without sources the discrete energy never
+    grows (Theorem for general boundary conditions, |gamma| <= 1), and the
+    GPU energy equals the oracle's energy of the same state."""
+    say("case: full-size 257x257x193 order 6 f32 energy over 10 steps")
+    wl = W.topo_layer()
+    shape = wl["xyz"].shape[1:]
+    Q = W.random_state(shape, 8, smooth=True)
+    s = make_solver(wl["xyz"], 6, "f32", wl["gamma"], medium=(wl["rho"], wl["cp"], wl["cs"]))
+    s.set_state(Q)
+    es = [s.energy()]
+    for _ in range(10):
+        s.step(1, wl["dt"])
+        es.append(s.energy())
+    last = s.get_state().cpu().numpy().astype(np.float64)
+    s.close()
+    say("  energies %s" % ["%.6e" % e for e in es])
+    for a, b in zip(es[:-1], es[1:]):
+        assert b <= a * (1 + 1e-6)
+    blk = E.Block(wl["xyz"], 6).set_material(wl["rho"], wl["cp"], wl["cs"])
+    eo = E.energy(blk, last)
+    assert abs(eo - es[-1]) <= 1e-5 * eo
+
+
+def test_launch_shapes_give_identical_results():
+    """Every node is computed by the same instructions whatever the tiling:
+    results are bitwise identical across z-chunk sizes and row counts."""
+    say("case: launch-shape invariance order 4 f32 40x37x29")
+    xyz = W.warped_mesh(70, 37, 29, seed=3)
+    med = W.random_medium((29, 37, 70), 4)
+    Q = W.random_state((29, 37, 70), 6, smooth=True)
+    outs = []
+    for ty, zc in ((8, 0), (8, 5), (4, 29), (4, 1)):
+        s = make_solver(xyz, 4, "f32", [0, 1, 0, 0, -1, 1], medium=med)
+        s.set_launch(ty, zc)
+        s.set_state(Q)
+        s.step(3, 1e-3)
+        outs.append(s.get_state().cpu().numpy())
+        s.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_resume_is_bitwise():
+    say("case: resume 20 + 20 == 40 steps, order 6 f32")
+    wl = W.topo_layer(nq=33, nr=29, ns=25)
+    med = (wl["rho"], wl["cp"], wl["cs"])
+    a = make_solver(wl["xyz"], 6, "f32", wl["gamma"], medium=med)
+    a.add_source(wl["src_xi"], wl["src_M"], 0, wl["src_f0"], wl["src_t0"])
+    a.step(40, wl["dt"])
+    ref = a.get_state().cpu().numpy()
+    a.close()
+    b = make_solver(wl["xyz"], 6, "f32", wl["gamma"], medium=med)
+    b.add_source(wl["src_xi"], wl["src_M"], 0, wl["src_f0"], wl["src_t0"])
+    b.step(20, wl["dt"])
+    mid = b.get_state()
+    t_mid = b.time()[0]
+    b.close()
+    c = make_solver(wl["xyz"], 6, "f32", wl["gamma"], medium=med)
+    c.add_source(wl["src_xi"], wl["src_M"], 0, wl["src_f0"], wl["src_t0"])
+    c.set_state(mid, t_mid)
+    c.step(20, wl["dt"])
+    out = c.get_state().cpu().numpy()
+    c.close()
+    assert np.array_equal(out, ref)
+
+
+def test_error_paths_on_device():
+    say("case: error paths")
+    sbp = sbp_mod()
+    xyz = W.unit_cube(13, 13, 13)
+    s = sbp.Solver(xyz, order=4, dtype="f32", gamma=[0] * 6)
+    with pytest.raises(sbp.SBPError) as e:
+        s.step(1, 1e-3)
+    assert e.value.code == sbp.SBP_ESTATE
+    s.set_material(2.7, 6.0, 3.464)
+    with pytest.raises(sbp.SBPError) as e:
+        s.add_source((0.5, 1.2, 0.5), (0, 0, 0, 1, 0, 0))
+    assert e.value.code == sbp.SBP_EINVAL
+    with pytest.raises(sbp.SBPError):
+        s.set_material(2.7, 3.0, 3.464)  # lambda + 2/3 mu < 0
+    s.record([(1, 2, 3)], 2)
+    s.step(2, 1e-3)
+    with pytest.raises(sbp.SBPError):
+        s.step(1, 1e-3)  # receiver buffer full
+    with pytest.raises(sbp.SBPError):
+        s.record([(13, 0, 0)], 2)
+    s.close()
+    bad = xyz.copy()
+    bad[0] = bad[0][:, :, ::-1]  # mirrored map: negative Jacobian
+    with pytest.raises(sbp.SBPError) as e:
+        sbp.Solver(bad, order=4, dtype="f32", gamma=[0] * 6)
+    assert e.value.code == sbp.SBP_EINVAL

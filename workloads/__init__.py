@@ -146,15 +146,19 @@ def random_state(shape, seed, smooth=False):
     if not smooth:
         return rng.standard_normal((9,) + tuple(shape))
     ns, nr, nq = shape
-    s, r, q = np.meshgrid(np.linspace(0, 1, ns), np.linspace(0, 1, nr), np.linspace(0, 1, nq),
-                          indexing="ij")
+    q = np.linspace(0, 1, nq)
+    r = np.linspace(0, 1, nr)
+    s = np.linspace(0, 1, ns)
     Q = np.zeros((9,) + tuple(shape))
     for f in range(9):
         for _ in range(3):
             k = rng.uniform(0.5, 3.0, size=3)
             ph = rng.uniform(0, 2 * np.pi, size=3)
-            Q[f] += rng.standard_normal() * np.cos(2 * np.pi * k[0] * q + ph[0]) \
-                * np.cos(2 * np.pi * k[1] * r + ph[1]) * np.cos(2 * np.pi * k[2] * s + ph[2])
+            a = rng.standard_normal()
+            cq = np.cos(2 * np.pi * k[0] * q + ph[0])
+            cr = np.cos(2 * np.pi * k[1] * r + ph[1])
+            cs = np.cos(2 * np.pi * k[2] * s + ph[2])
+            Q[f] += a * cs[:, None, None] * cr[None, :, None] * cq[None, None, :]
     return Q
 
 
