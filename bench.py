@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ty", type=int, default=8)
     ap.add_argument("--zchunk", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (x4) for HBM counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver is a single-block, single-GPU build "
@@ -106,6 +108,15 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read_per_copy": 4 * n, "copies": 4}))
+        return
     print("bench: generating workload", file=sys.stderr, flush=True)
     wl = W.topo_layer()
     ns, nr, nq = wl["xyz"].shape[1:]

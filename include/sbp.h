@@ -180,7 +180,7 @@ int sbp_energy(sbp_handle h, double* E);
 
 /*
  * Launch shape of the stage kernel: ty rows of 64 points per thread block
- * (4 or 8) and zchunk planes per block along s (>= 1; 0 = automatic).
+ * (8 or 16) and zchunk planes per block along s (>= 1; 0 = automatic).
  * Does not change results beyond floating-point summation order (it does
  * not change it at all: every node is computed by the same instructions).
  */

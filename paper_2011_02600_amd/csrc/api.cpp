@@ -80,7 +80,7 @@ struct sbp_ctx {
   std::size_t ws_bytes = 0;
   // byte offsets in the workspace
   std::size_t off_qa = 0, off_qb = 0, off_dq = 0, off_coef = 0, off_face[6] = {}, off_src = 0,
-              off_rec = 0, off_part = 0, off_bounds = 0, total = 0;
+              off_rec = 0, off_part = 0, off_bounds = 0, off_tab = 0, total = 0;
   std::size_t face_n[6] = {};
   int px = 0;
   std::size_t plane = 0, field = 0;
@@ -142,6 +142,7 @@ void layout(sbp_ctx* h) {
   h->off_rec = take((std::size_t)kMaxRec * sizeof(long long));
   h->off_part = take(kMaxPart * sizeof(double));
   h->off_bounds = take((std::size_t)(g.nq + g.nr + g.ns + 16) * sizeof(int));
+  h->off_tab = take((std::size_t)kClosureTab * kMaxM * kMaxCols * es);
   h->total = o;
 }
 
@@ -314,11 +315,12 @@ int prepare_bounds(sbp_ctx* h) {
   h->nyt = (int)yb.size() - 1;
   int zc = h->zchunk;
   if (zc <= 0) {
-    // aim at >= 8 resident blocks per compute unit on 256 CUs
-    const long long want = 2048;
+    // one resident wave of blocks: two blocks of 8 rows (or one of 16) per
+    // compute unit on 256 compute units, split along s
+    const long long slots = h->ty == 8 ? 512 : 256;
     const long long cols = (long long)h->nxt * h->nyt;
-    long long nz = (want + cols - 1) / cols;
-    nz = std::max(1LL, std::min(nz, (long long)g.ns / 16 > 0 ? (long long)g.ns / 16 : 1LL));
+    long long nz = std::max(1LL, slots / cols);
+    nz = std::min(nz, (long long)std::max(1, g.ns / 8));
     zc = (int)((g.ns + nz - 1) / nz);
   }
   zc = std::max(1, std::min(zc, g.ns));
@@ -370,11 +372,7 @@ StageArgs<T> stage_args(sbp_ctx* h) {
   a.inv_h[0] = (T)(g.nq - 1);
   a.inv_h[1] = (T)(g.nr - 1);
   a.inv_h[2] = (T)(g.ns - 1);
-  for (int i = 0; i < kMaxM; ++i)
-    for (int c = 0; c < kMaxCols; ++c) {
-      a.dp[i][c] = (T)h->cl.dp[i][c];
-      a.dm[i][c] = (T)h->cl.dm[i][c];
-    }
+  a.tab = (const T*)(h->ws + h->off_tab);
   return a;
 }
 
@@ -539,6 +537,26 @@ int sbp_init_grid(sbp_handle* out, int nq, int nr, int ns, const double* xyz, in
   if (!build_closure(order, &h->cl, &err)) {
     delete h;
     return fail(SBP_EINVAL, "closure construction failed: %s", err);
+  }
+  {
+    // closure rows: h D+ and h D- at the left end, then their negatives,
+    // which are the right-end rows of h D+ and h D- against reversed columns
+    std::vector<double> tab((std::size_t)kClosureTab * kMaxM * kMaxCols, 0.0);
+    for (int r = 0; r < kMaxM; ++r)
+      for (int c = 0; c < kMaxCols; ++c) {
+        const std::size_t o = (std::size_t)r * kMaxCols + c;
+        tab[0 * kMaxM * kMaxCols + o] = h->cl.dp[r][c];
+        tab[1 * kMaxM * kMaxCols + o] = h->cl.dm[r][c];
+        tab[2 * kMaxM * kMaxCols + o] = -h->cl.dm[r][c];
+        tab[3 * kMaxM * kMaxCols + o] = -h->cl.dp[r][c];
+      }
+    rc = upload_vec(h, h->off_tab, tab);
+    if (rc) {
+      std::string keep = g_err;
+      delete h;
+      g_err = keep;
+      return rc;
+    }
   }
   // zero the state buffers and the Runge-Kutta register
   hipError_t e = hipMemsetAsync(h->ws, 0, h->off_coef, h->stream);
@@ -748,7 +766,7 @@ int sbp_energy(sbp_handle h, double* E) {
 
 int sbp_set_launch(sbp_handle h, int ty, int zchunk) {
   if (!h) return fail(SBP_EINVAL, "NULL handle");
-  if (ty != 4 && ty != 8) return fail(SBP_EINVAL, "ty must be 4 or 8");
+  if (ty != 8 && ty != 16) return fail(SBP_EINVAL, "ty must be 8 or 16");
   if (ty < h->cl.m) return fail(SBP_EINVAL, "ty must be >= %d for order %d", h->cl.m, h->order);
   if (zchunk < 0) return fail(SBP_EINVAL, "zchunk must be >= 0");
   h->ty = ty;

@@ -48,6 +48,59 @@ struct Stencil<6> {
 };
 
 // ---------------------------------------------------------------------------
+// element `off` of the field starting at the uniform address `base`: the byte
+// offset is formed in 32 bits so that the load uses a scalar base address plus
+// a 32-bit vector offset (fields are smaller than 4 GiB)
+template <typename T>
+__device__ __forceinline__ T ldf(const T* base, unsigned off) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + (unsigned)(off * sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void stf(T* base, unsigned off, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + (unsigned)(off * sizeof(T))) = v;
+}
+
+// Field array accessor: BUF = true uses a buffer resource (one descriptor per
+// array, the field offset in a scalar register, the element offset as a
+// 32-bit vector offset; the array must be smaller than 4 GiB); BUF = false
+// uses plain pointers.
+template <typename T, bool BUF>
+struct Arr;
+
+template <typename T>
+struct Arr<T, true> {
+  __amdgpu_buffer_rsrc_t r;
+  unsigned fbytes;
+  __device__ Arr(const T* p, std::size_t field)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), (short)0, -1, 0x00020000)),
+        fbytes((unsigned)(field * sizeof(T))) {}
+  __device__ __forceinline__ T ld(int c, unsigned off) const {
+    if constexpr (sizeof(T) == 4) {
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(off * 4u), (int)(c * fbytes), 0));
+    } else {
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(off * 8u), (int)(c * fbytes), 0));
+    }
+  }
+  __device__ __forceinline__ void st(int c, unsigned off, T v) const {
+    if constexpr (sizeof(T) == 4) {
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)(off * 4u), (int)(c * fbytes), 0);
+    } else {
+      using u2 = unsigned __attribute__((ext_vector_type(2)));
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)(off * 8u), (int)(c * fbytes), 0);
+    }
+  }
+};
+
+template <typename T>
+struct Arr<T, false> {
+  T* p;
+  std::size_t field;
+  __device__ Arr(const T* p_, std::size_t f) : p(const_cast<T*>(p_)), field(f) {}
+  __device__ __forceinline__ T ld(int c, unsigned off) const { return ldf(p + c * field, off); }
+  __device__ __forceinline__ void st(int c, unsigned off, T v) const { stf(p + c * field, off, v); }
+};
+
+// ---------------------------------------------------------------------------
 // boundary penalty at one face node, accumulated into rate[9]
 template <typename T>
 __device__ __forceinline__ void face_penalty(const T* __restrict__ fc, std::size_t fstride,
@@ -96,21 +149,42 @@ __device__ __forceinline__ void face_penalty(const T* __restrict__ fc, std::size
 
 // ---------------------------------------------------------------------------
 // the fused stage kernel
-template <typename T, int ORDER, int TY>
-__global__ __launch_bounds__(64 * TY) void stage_kernel(StageArgs<T> A) {
+//
+// Per plane a of the block's chunk:
+//   phase 1  load plane a: own sigma and q/r metric rows (q/r fluxes), the
+//            y-halo and x-halo points of the tile, the s-flux of the lead
+//            plane a+1+R (into the LDS ring) and the lead velocity a+1+Q;
+//            stage v, F_q, F_r in LDS
+//   phase 2  derivatives (LDS along q and r, the v register queue and the
+//            F_s LDS ring along s), rates, penalties, stage update, stores
+// LDS: v window (64+2H) x (TY+2H), F_q window (64+2H) x TY, F_r window
+// 64 x (TY+2H), and a per-thread ring of QD planes of F_s.
+// All offsets inside one field are 32-bit; field bases are uniform.
+#ifndef SBP_STAGE_MIN_WAVES
+#define SBP_STAGE_MIN_WAVES 1  // minimum waves per SIMD the register allocation must allow
+#endif
+template <typename T, int ORDER, int TY, bool BUF>
+__global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(const StageArgs<T> A) {
   using S = Stencil<ORDER>;
   constexpr int R = S::R, Q = S::Q, M = S::M;
-  constexpr int H = Q;            // LDS halo width (Q >= R)
-  constexpr int WX = 64 + 2 * H;  // LDS window
-  constexpr int WY = TY + 2 * H;
-  constexpr int WN = WX * WY;
-  constexpr int QD = R + Q + 1;   // register queue depth
-  constexpr int NT = 64 * TY;
-  __shared__ T lds[9 * WN];  // v (3), q-flux (3), r-flux (3)
+  constexpr int H = Q;            // halo width (Q >= R)
+  constexpr int NT = 64 * TY;     // threads
+  constexpr int VX = 64 + 2 * H, VY = TY + 2 * H;  // v window
+  constexpr int QX = 64 + 2 * H;                   // F_q window (TY rows)
+  constexpr int RX = 64;                           // F_r window (VY rows)
+  constexpr int QD = R + Q + 1;   // s queue depth
+  constexpr int NYH = 2 * H * 64; // y-halo points
+  constexpr int NXH = 2 * H * TY; // x-halo points
+  constexpr int TABN = kMaxM * kMaxCols;
+  static_assert(NYH <= NT, "one y-halo point per thread");
+  static_assert(TY >= M, "r closure rows must fit in one tile");
+  __shared__ T lv[3 * VX * VY];
+  __shared__ T lq[3 * QX * TY];
+  __shared__ T lr[3 * RX * VY];
+  __shared__ T ring[QD * 3 * NT];
 
   // XCD-aware tile order: consecutive tiles land on the same XCD
-  const int nb = gridDim.x;
-  const int per = nb >> 3;
+  const int per = gridDim.x >> 3;
   const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (tile >= A.ntiles) return;
   const int xt = tile % A.nxt;
@@ -126,169 +200,236 @@ __global__ __launch_bounds__(64 * TY) void stage_kernel(StageArgs<T> A) {
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * 64 + tx;
   const int i = x0 + tx, j = y0 + ty;
-  const bool act = (i < x1) && (j < y1);
   const int nq = A.nq, nr = A.nr, ns = A.ns;
-  const std::size_t px = A.px, plane = A.plane, field = A.field;
-  const std::size_t col = (std::size_t)j * px + i;  // offset of (i, j) in a plane
+  const bool act = (i < x1) && (j < y1);    // node computed by this block
+  const bool ing = (i < nq) && (j < nr);    // node staged in LDS (own or halo of the tile)
+  const unsigned px = A.px, plane = A.plane;
+  const std::size_t field = A.field;
+  const unsigned col = (unsigned)j * px + (unsigned)i;
 
-  const T* __restrict__ qin = A.qin;
-  const T* __restrict__ cf = A.coef;
+  const Arr<T, BUF> gq(A.qin, field), gc(A.coef, field), gd(A.dq, field), go(A.qout, field);
+  const T* __restrict__ tab = A.tab;
 
-  // s-flux F_s,i = sum_c M[s][c] sigma_ic at (i, j, k)
-  auto sflux = [&](int k, T f[3]) {
-    const std::size_t o = (std::size_t)k * plane + col;
-    const T m0 = cf[6 * field + o], m1 = cf[7 * field + o], m2 = cf[8 * field + o];
-    const T sxx = qin[3 * field + o], syy = qin[4 * field + o], szz = qin[5 * field + o];
-    const T sxy = qin[6 * field + o], sxz = qin[7 * field + o], syz = qin[8 * field + o];
+  // y halo: rows y0-H..y0-1 and y0+TY..y0+TY+H-1, columns x0..x0+63
+  const int yh_r = tid >> 6;
+  const int yh_gy = (yh_r < H) ? (y0 - H + yh_r) : (y0 + TY + yh_r - H);
+  const int yh_gx = x0 + (tid & 63);
+  const bool yh_in = tid < NYH && yh_gx < nq && yh_gy >= 0 && yh_gy < nr;
+  const int yh_ly = (yh_r < H) ? yh_r : TY + yh_r;   // row in the v / F_r windows
+  const unsigned yh_col = yh_in ? (unsigned)yh_gy * px + (unsigned)yh_gx : 0u;
+  // x halo: columns x0-H..x0-1 and x0+64..x0+64+H-1, rows y0..y0+TY-1
+  const int xh_c = tid / TY;
+  const int xh_r = tid - xh_c * TY;
+  const int xh_gx = (xh_c < H) ? (x0 - H + xh_c) : (x0 + 64 + xh_c - H);
+  const int xh_gy = y0 + xh_r;
+  const bool xh_in = tid < NXH && xh_gx >= 0 && xh_gx < nq && xh_gy < nr;
+  const int xh_lx = (xh_c < H) ? xh_c : 64 + xh_c;  // column in the v / F_q windows
+  const unsigned xh_col = xh_in ? (unsigned)xh_gy * px + (unsigned)xh_gx : 0u;
+
+  // s-flux F_s,i = sum_c M[s][c] sigma_ic
+  auto sflux = [&](unsigned o, T f[3]) {
+    const T m0 = gc.ld(6, o), m1 = gc.ld(7, o), m2 = gc.ld(8, o);
+    const T sxx = gq.ld(3, o), syy = gq.ld(4, o), szz = gq.ld(5, o);
+    const T sxy = gq.ld(6, o), sxz = gq.ld(7, o), syz = gq.ld(8, o);
     f[0] = m0 * sxx + m1 * sxy + m2 * sxz;
     f[1] = m0 * sxy + m1 * syy + m2 * syz;
     f[2] = m0 * sxz + m1 * syz + m2 * szz;
   };
+  // ring slot of plane k (k >= -Q)
+  auto slot = [&](int k) { return (k + 7 * QD) % QD; };
 
-  // register queues: vq[s] = v(a - R + s), fq[t] = F_s(a - Q + t)
-  T vq[3][QD], fq[3][QD];
+  // register queue vq[s] = v(a - R + s); ring holds F_s(a - Q .. a + R)
+  T vq[3][QD];
 #pragma unroll
-  for (int s = 0; s < QD; ++s) {
+  for (int s = 0; s < QD; ++s)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) { vq[c][s] = T(0); fq[c][s] = T(0); }
-  }
-  if (act) {
+    for (int c = 0; c < 3; ++c) vq[c][s] = T(0);
+  if (ing) {
 #pragma unroll
     for (int s = 0; s < QD; ++s) {
       const int kv = z0 - R + s;
       if (kv >= 0 && kv < ns) {
-        const std::size_t o = (std::size_t)kv * plane + col;
+        const unsigned o = (unsigned)kv * plane + col;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) vq[c][s] = qin[c * field + o];
+        for (int c = 0; c < 3; ++c) vq[c][s] = gq.ld(c, o);
       }
+    }
+    for (int s = 0; s < QD; ++s) {
       const int kf = z0 - Q + s;
-      if (kf >= 0 && kf < ns) {
-        T f[3];
-        sflux(kf, f);
+      T f[3] = {T(0), T(0), T(0)};
+      if (kf >= 0 && kf < ns) sflux((unsigned)kf * plane + col, f);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) fq[c][s] = f[c];
-      }
+      for (int c = 0; c < 3; ++c) ring[(slot(kf) * 3 + c) * NT + tid] = f[c];
     }
   }
 
-  const int lx = tx + H, ly = ty + H;  // own LDS position
+  const int vme = (ty + H) * VX + tx + H;   // own position in the v window
+  const int qme = ty * QX + tx + H;         // ... F_q window
+  const int rme = (ty + H) * RX + tx;       // ... F_r window
   const T ihq = A.inv_h[0], ihr = A.inv_h[1], ihs = A.inv_h[2];
+  const bool xin = i >= M && i < nq - M;
+  const bool yin = j >= M && j < nr - M;
+  const int xrow = (i < M) ? i : nq - 1 - i;
+  const int yrow = (j < M) ? j : nr - 1 - j;
+  const T* __restrict__ xtab = tab + ((i < M) ? 0 : 2 * TABN);
+  const T* __restrict__ ytab = tab + ((j < M) ? 0 : 2 * TABN);
+  const int ncol = A.ncol;
 
   for (int a = z0; a < z1; ++a) {
-    const std::size_t pa = (std::size_t)a * plane;
-    // ---- stage v, q-flux, r-flux of plane a (tile + halo) into LDS
-    for (int p = tid; p < WN; p += NT) {
-      const int wy = p / WX, wx = p - wy * WX;
-      const int gx = x0 - H + wx, gy = y0 - H + wy;
-      T vals[9];
+    const unsigned pa = (unsigned)a * plane;
+    const unsigned o = pa + col;
+    // ---------------- phase 1
+    T sg[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+    T mq[3] = {T(0), T(0), T(0)}, mr[3] = {T(0), T(0), T(0)};
+    T lead_v[3] = {T(0), T(0), T(0)}, lead_f[3] = {T(0), T(0), T(0)};
+    if (ing) {
 #pragma unroll
-      for (int c = 0; c < 9; ++c) vals[c] = T(0);
-      if (gx >= 0 && gx < nq && gy >= 0 && gy < nr) {
-        const std::size_t o = pa + (std::size_t)gy * px + gx;
-        const T sxx = qin[3 * field + o], syy = qin[4 * field + o], szz = qin[5 * field + o];
-        const T sxy = qin[6 * field + o], sxz = qin[7 * field + o], syz = qin[8 * field + o];
-        const T q0 = cf[0 * field + o], q1 = cf[1 * field + o], q2 = cf[2 * field + o];
-        const T r0 = cf[3 * field + o], r1 = cf[4 * field + o], r2 = cf[5 * field + o];
-        vals[0] = qin[o];
-        vals[1] = qin[field + o];
-        vals[2] = qin[2 * field + o];
-        vals[3] = q0 * sxx + q1 * sxy + q2 * sxz;
-        vals[4] = q0 * sxy + q1 * syy + q2 * syz;
-        vals[5] = q0 * sxz + q1 * syz + q2 * szz;
-        vals[6] = r0 * sxx + r1 * sxy + r2 * sxz;
-        vals[7] = r0 * sxy + r1 * syy + r2 * syz;
-        vals[8] = r0 * sxz + r1 * syz + r2 * szz;
+      for (int c = 0; c < 6; ++c) sg[c] = gq.ld(3 + c, o);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) { mq[c] = gc.ld(c, o); mr[c] = gc.ld(3 + c, o); }
+      lv[0 * VX * VY + vme] = vq[0][R];
+      lv[1 * VX * VY + vme] = vq[1][R];
+      lv[2 * VX * VY + vme] = vq[2][R];
+      lq[0 * QX * TY + qme] = mq[0] * sg[0] + mq[1] * sg[3] + mq[2] * sg[4];
+      lq[1 * QX * TY + qme] = mq[0] * sg[3] + mq[1] * sg[1] + mq[2] * sg[5];
+      lq[2 * QX * TY + qme] = mq[0] * sg[4] + mq[1] * sg[5] + mq[2] * sg[2];
+      lr[0 * RX * VY + rme] = mr[0] * sg[0] + mr[1] * sg[3] + mr[2] * sg[4];
+      lr[1 * RX * VY + rme] = mr[0] * sg[3] + mr[1] * sg[1] + mr[2] * sg[5];
+      lr[2 * RX * VY + rme] = mr[0] * sg[4] + mr[1] * sg[5] + mr[2] * sg[2];
+      const int kv = a + 1 + Q;
+      if (kv < ns) {
+        const unsigned ov = (unsigned)kv * plane + col;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) lead_v[c] = gq.ld(c, ov);
       }
+      // the lead plane's ring slot is still read in phase 2 (plane a - Q):
+      // keep its flux in registers until the queue advance
+      const int kf = a + 1 + R;
+      if (kf < ns) sflux((unsigned)kf * plane + col, lead_f);
+    }
+    if (yh_in) {  // v and r-flux of a y-halo point
+      const unsigned oh = pa + yh_col;
+      T h[12];
 #pragma unroll
-      for (int c = 0; c < 9; ++c) lds[c * WN + p] = vals[c];
+      for (int c = 0; c < 9; ++c) h[c] = gq.ld(c, oh);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) h[9 + c] = gc.ld(3 + c, oh);
+      const int wv = yh_ly * VX + (tid & 63) + H;
+      const int wr = yh_ly * RX + (tid & 63);
+      lv[0 * VX * VY + wv] = h[0];
+      lv[1 * VX * VY + wv] = h[1];
+      lv[2 * VX * VY + wv] = h[2];
+      lr[0 * RX * VY + wr] = h[9] * h[3] + h[10] * h[6] + h[11] * h[7];
+      lr[1 * RX * VY + wr] = h[9] * h[6] + h[10] * h[4] + h[11] * h[8];
+      lr[2 * RX * VY + wr] = h[9] * h[7] + h[10] * h[8] + h[11] * h[5];
+    }
+    if (xh_in) {  // v and q-flux of an x-halo point
+      const unsigned oh = pa + xh_col;
+      T h[12];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) h[c] = gq.ld(c, oh);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) h[9 + c] = gc.ld(c, oh);
+      const int wv = (xh_r + H) * VX + xh_lx;
+      const int wq = xh_r * QX + xh_lx;
+      lv[0 * VX * VY + wv] = h[0];
+      lv[1 * VX * VY + wv] = h[1];
+      lv[2 * VX * VY + wv] = h[2];
+      lq[0 * QX * TY + wq] = h[9] * h[3] + h[10] * h[6] + h[11] * h[7];
+      lq[1 * QX * TY + wq] = h[9] * h[6] + h[10] * h[4] + h[11] * h[8];
+      lq[2 * QX * TY + wq] = h[9] * h[7] + h[10] * h[8] + h[11] * h[5];
     }
     __syncthreads();
 
+    // ---------------- phase 2
     if (act) {
-      T u[3][3];   // u[xi][c] = D+_xi v_c (times 1/h_xi applied below)
+      T ms[3], dqo[9];
+      for (int c = 0; c < 3; ++c) ms[c] = gc.ld(6 + c, o);
+      const T lamJ = gc.ld(9, o), muJ = gc.ld(10, o), rJ = gc.ld(11, o);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) dqo[c] = A.read_dq ? gd.ld(c, o) : T(0);
+      T u[3][3];   // u[xi][c] = D+_xi v_c
       T dv[3];     // sum_xi D-_xi F_xi,c
-      const T* lv = lds;
-      const T* lfq = lds + 3 * WN;
-      const T* lfr = lds + 6 * WN;
-      const int me = ly * WX + lx;
-      // ---- q direction (LDS row)
-      if (i >= M && i < nq - M) {
+      // q direction
+      if (__builtin_expect(xin, 1)) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           T sp = T(0), sm = T(0);
 #pragma unroll
           for (int s = 0; s < QD; ++s) {
-            sp += T(S::a[s]) * lv[c * WN + me - R + s];
-            sm += T(S::a[s]) * lfq[c * WN + me + R - s];
+            sp += T(S::a[s]) * lv[c * VX * VY + vme - R + s];
+            sm += T(S::a[s]) * lq[c * QX * TY + qme + R - s];
           }
           u[0][c] = sp * ihq;
           dv[c] = -sm * ihq;
         }
       } else {
+        T sp[3] = {T(0), T(0), T(0)}, sm[3] = {T(0), T(0), T(0)};
         const bool left = i < M;
-        const int row = left ? i : nq - 1 - i;
-        const int rowbase = ly * WX;
+        const int gv = (ty + H) * VX + H - x0 + (left ? 0 : nq - 1);
+        const int gq = ty * QX + H - x0 + (left ? 0 : nq - 1);
+        const int step = left ? 1 : -1;
+        for (int cc = 0; cc < ncol; ++cc) {
+          const T cp = xtab[xrow * kMaxCols + cc];
+          const T cm = xtab[TABN + xrow * kMaxCols + cc];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            sp[c] += cp * lv[c * VX * VY + gv + step * cc];
+            sm[c] += cm * lq[c * QX * TY + gq + step * cc];
+          }
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          T sp = T(0), sm = T(0);
-          for (int cc = 0; cc < A.ncol; ++cc) {
-            const int gcol = left ? cc : nq - 1 - cc;
-            const int w = rowbase + gcol - x0 + H;
-            if (left) {
-              sp += A.dp[row][cc] * lv[c * WN + w];
-              sm += A.dm[row][cc] * lfq[c * WN + w];
-            } else {
-              sp -= A.dm[row][cc] * lv[c * WN + w];
-              sm -= A.dp[row][cc] * lfq[c * WN + w];
-            }
-          }
-          u[0][c] = sp * ihq;
-          dv[c] = sm * ihq;
+          u[0][c] = sp[c] * ihq;
+          dv[c] = sm[c] * ihq;
         }
       }
-      // ---- r direction (LDS column)
-      if (j >= M && j < nr - M) {
+      // r direction
+      if (__builtin_expect(yin, 1)) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           T sp = T(0), sm = T(0);
 #pragma unroll
           for (int s = 0; s < QD; ++s) {
-            sp += T(S::a[s]) * lv[c * WN + me + (s - R) * WX];
-            sm += T(S::a[s]) * lfr[c * WN + me + (R - s) * WX];
+            sp += T(S::a[s]) * lv[c * VX * VY + vme + (s - R) * VX];
+            sm += T(S::a[s]) * lr[c * RX * VY + rme + (R - s) * RX];
           }
           u[1][c] = sp * ihr;
           dv[c] -= sm * ihr;
         }
       } else {
+        T sp[3] = {T(0), T(0), T(0)}, sm[3] = {T(0), T(0), T(0)};
         const bool left = j < M;
-        const int row = left ? j : nr - 1 - j;
+        const int rowv = H - y0 + (left ? 0 : nr - 1);
+        const int stepr = left ? 1 : -1;
+        for (int cc = 0; cc < ncol; ++cc) {
+          const T cp = ytab[yrow * kMaxCols + cc];
+          const T cm = ytab[TABN + yrow * kMaxCols + cc];
+          const int rw = rowv + stepr * cc;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            sp[c] += cp * lv[c * VX * VY + rw * VX + tx + H];
+            sm[c] += cm * lr[c * RX * VY + rw * RX + tx];
+          }
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          T sp = T(0), sm = T(0);
-          for (int cc = 0; cc < A.ncol; ++cc) {
-            const int grow = left ? cc : nr - 1 - cc;
-            const int w = (grow - y0 + H) * WX + lx;
-            if (left) {
-              sp += A.dp[row][cc] * lv[c * WN + w];
-              sm += A.dm[row][cc] * lfr[c * WN + w];
-            } else {
-              sp -= A.dm[row][cc] * lv[c * WN + w];
-              sm -= A.dp[row][cc] * lfr[c * WN + w];
-            }
-          }
-          u[1][c] = sp * ihr;
-          dv[c] += sm * ihr;
+          u[1][c] = sp[c] * ihr;
+          dv[c] += sm[c] * ihr;
         }
       }
-      // ---- s direction
-      if (a >= M && a < ns - M) {
+      // s direction
+      if (__builtin_expect(a >= M && a < ns - M, 1)) {
+        const int s0 = slot(a - Q);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           T sp = T(0), sm = T(0);
 #pragma unroll
           for (int s = 0; s < QD; ++s) {
             sp += T(S::a[s]) * vq[c][s];
-            sm += T(S::a[s]) * fq[c][R + Q - s];
+            int t = s0 + R + Q - s;
+            t = t >= QD ? t - QD : t;
+            sm += T(S::a[s]) * ring[(t * 3 + c) * NT + tid];
           }
           u[2][c] = sp * ihs;
           dv[c] -= sm * ihs;
@@ -296,17 +437,18 @@ __global__ __launch_bounds__(64 * TY) void stage_kernel(StageArgs<T> A) {
       } else {
         const bool left = a < M;
         const int row = left ? a : ns - 1 - a;
+        const T* __restrict__ zt = tab + (left ? 0 : 2 * TABN);
         T sp[3] = {T(0), T(0), T(0)}, sm[3] = {T(0), T(0), T(0)};
-        for (int cc = 0; cc < A.ncol; ++cc) {
+        for (int cc = 0; cc < ncol; ++cc) {
           const int k = left ? cc : ns - 1 - cc;
-          const std::size_t o = (std::size_t)k * plane + col;
+          const unsigned ok = (unsigned)k * plane + col;
           T f[3];
-          sflux(k, f);
-          const T cp = left ? A.dp[row][cc] : -A.dm[row][cc];
-          const T cm = left ? A.dm[row][cc] : -A.dp[row][cc];
+          sflux(ok, f);
+          const T cp = zt[row * kMaxCols + cc];
+          const T cm = zt[TABN + row * kMaxCols + cc];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            sp[c] += cp * qin[c * field + o];
+            sp[c] += cp * gq.ld(c, ok);
             sm[c] += cm * f[c];
           }
         }
@@ -317,20 +459,12 @@ __global__ __launch_bounds__(64 * TY) void stage_kernel(StageArgs<T> A) {
         }
       }
 
-      // ---- pointwise: stress rates (non-conservative metric form + Hooke)
-      const std::size_t o = pa + col;
-      T Mm[3][3];
-#pragma unroll
-      for (int xi = 0; xi < 3; ++xi)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) Mm[xi][c] = cf[(3 * xi + c) * field + o];
-      const T lamJ = cf[9 * field + o], muJ = cf[10 * field + o], rJ = cf[11 * field + o];
-      T G[3][3];  // G[c][i] = sum_xi M[xi][c] u[xi][i]  (= J dv_i/dx_c)
+      // pointwise: stress rates (non-conservative metric form + Hooke)
+      T G[3][3];  // G[c][ii] = sum_xi M[xi][c] u[xi][ii]  (= J dv_ii/dx_c)
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int ii = 0; ii < 3; ++ii)
-          G[c][ii] = Mm[0][c] * u[0][ii] + Mm[1][c] * u[1][ii] + Mm[2][c] * u[2][ii];
+        for (int ii = 0; ii < 3; ++ii) G[c][ii] = mq[c] * u[0][ii] + mr[c] * u[1][ii] + ms[c] * u[2][ii];
       const T div = G[0][0] + G[1][1] + G[2][2];
       T rate[9];
       rate[0] = rJ * dv[0];
@@ -343,12 +477,9 @@ __global__ __launch_bounds__(64 * TY) void stage_kernel(StageArgs<T> A) {
       rate[7] = muJ * (G[2][0] + G[0][2]);
       rate[8] = muJ * (G[2][1] + G[1][2]);
 
-      T v[3] = {vq[0][R], vq[1][R], vq[2][R]};
-      T sg[6];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) sg[c] = qin[(3 + c) * field + o];
+      const T v[3] = {vq[0][R], vq[1][R], vq[2][R]};
 
-      // ---- boundary penalties (faces q0, q1, r0, r1, s0, s1)
+      // boundary penalties (faces q0, q1, r0, r1, s0, s1)
       if (i == 0 || i == nq - 1 || j == 0 || j == nr - 1 || a == 0 || a == ns - 1) {
         if (i == 0)
           face_penalty(A.face + A.face_off[0] + ((std::size_t)a * nr + j), A.face_n[0], A.gamma[0],
@@ -370,42 +501,31 @@ __global__ __launch_bounds__(64 * TY) void stage_kernel(StageArgs<T> A) {
                        T(1), A.traction[5], v, sg, rate);
       }
 
-      // ---- Runge-Kutta stage update
-      T* __restrict__ dq = A.dq;
-      T* __restrict__ qout = A.qout;
+      // Runge-Kutta stage update
       const T dt = A.dt, Ak = A.Ak, Bk = A.Bk;
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
-        T d = dt * rate[c];
-        if (A.read_dq) d += Ak * dq[c * field + o];
-        dq[c * field + o] = d;
+        const T d = dt * rate[c] + Ak * dqo[c];
+        gd.st(c, o, d);
         const T q0 = (c < 3) ? v[c] : sg[c - 3];
-        qout[c * field + o] = q0 + Bk * d;
-      }
-    }
-
-    // ---- advance the s queues to plane a + 1
-    if (act) {
-#pragma unroll
-      for (int s = 0; s < QD - 1; ++s) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) { vq[c][s] = vq[c][s + 1]; fq[c][s] = fq[c][s + 1]; }
-      }
-      const int kv = a + 1 + Q;
-      if (kv < ns) {
-        const std::size_t oo = (std::size_t)kv * plane + col;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) vq[c][QD - 1] = qin[c * field + oo];
-      }
-      const int kf = a + 1 + R;
-      if (kf < ns) {
-        T f[3];
-        sflux(kf, f);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) fq[c][QD - 1] = f[c];
+        go.st(c, o, q0 + Bk * d);
       }
     }
     __syncthreads();
+
+    // advance the s queues to plane a + 1 (the ring slot of plane a - Q
+    // becomes that of plane a + 1 + R; each thread touches only its own slots)
+#pragma unroll
+    for (int s = 0; s < QD - 1; ++s)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) vq[c][s] = vq[c][s + 1];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vq[c][QD - 1] = lead_v[c];
+    if (ing) {
+      const int sl = slot(a + 1 + R);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ring[(sl * 3 + c) * NT + tid] = lead_f[c];
+    }
   }
 }
 
@@ -483,21 +603,30 @@ __global__ void energy_kernel(EnergyArgs<T> E) {
 // launchers
 template <typename T, int ORDER, int TY>
 static hipError_t launch_stage_t(const StageArgs<T>& a, hipStream_t st) {
-  const int nb = ((a.ntiles + 7) / 8) * 8;
-  hipLaunchKernelGGL((stage_kernel<T, ORDER, TY>), dim3(nb), dim3(64, TY), 0, st, a);
-  return hipGetLastError();
+  if constexpr (sizeof(T) == 8 && TY == 16) {
+    return hipErrorInvalidValue;
+  } else {
+    const int nb = ((a.ntiles + 7) / 8) * 8;
+    // buffer addressing needs every array (at most 12 fields) below 4 GiB
+    if (12.0 * (double)a.field * sizeof(T) < 4294967296.0)
+      hipLaunchKernelGGL((stage_kernel<T, ORDER, TY, true>), dim3(nb), dim3(64, TY), 0, st, a);
+    else
+      hipLaunchKernelGGL((stage_kernel<T, ORDER, TY, false>), dim3(nb), dim3(64, TY), 0, st, a);
+    return hipGetLastError();
+  }
 }
 
 template <typename T>
 hipError_t launch_stage(int order, int ty, const StageArgs<T>& a, hipStream_t st) {
-  if (ty == 8) {
+  // 16-row tiles only for 4-byte types (LDS capacity)
+  if (ty == 16 && sizeof(T) == 4) {
+    if (order == 2) return launch_stage_t<T, 2, 16>(a, st);
+    if (order == 4) return launch_stage_t<T, 4, 16>(a, st);
+    if (order == 6) return launch_stage_t<T, 6, 16>(a, st);
+  } else {
     if (order == 2) return launch_stage_t<T, 2, 8>(a, st);
     if (order == 4) return launch_stage_t<T, 4, 8>(a, st);
     if (order == 6) return launch_stage_t<T, 6, 8>(a, st);
-  } else if (ty == 4) {
-    if (order == 2) return launch_stage_t<T, 2, 4>(a, st);
-    if (order == 4) return launch_stage_t<T, 4, 4>(a, st);
-    if (order == 6) return launch_stage_t<T, 6, 4>(a, st);
   }
   return hipErrorInvalidValue;
 }

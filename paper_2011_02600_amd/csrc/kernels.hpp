@@ -28,9 +28,13 @@ struct StageArgs {
   T Ak, Bk, dt;
   T inv_h[3];
   T gamma[6];
-  T dp[kMaxM][kMaxCols];  // closure rows of h D+ (left end)
-  T dm[kMaxM][kMaxCols];  // closure rows of h D- (left end)
+  // closure rows, kClosureTab blocks of kMaxM x kMaxCols values: h D+ and
+  // h D- at the left end, then -h D- and -h D+ (the right-end rows of h D+
+  // and h D- read against reversed columns)
+  const T* tab;
 };
+
+constexpr int kClosureTab = 4;
 
 template <typename T>
 struct SourceArgs {

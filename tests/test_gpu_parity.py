@@ -213,7 +213,7 @@ def test_launch_shapes_give_identical_results():
     med = W.random_medium((29, 37, 70), 4)
     Q = W.random_state((29, 37, 70), 6, smooth=True)
     outs = []
-    for ty, zc in ((8, 0), (8, 5), (4, 29), (4, 1)):
+    for ty, zc in ((8, 0), (8, 5), (16, 29), (16, 1)):
         s = make_solver(xyz, 4, "f32", [0, 1, 0, 0, -1, 1], medium=med)
         s.set_launch(ty, zc)
         s.set_state(Q)

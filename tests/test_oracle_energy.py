@@ -200,3 +200,41 @@ def test_energy_decays_in_time_without_sources():
         e = E.energy(blk, Q)
         assert e <= e_prev * (1 + 1e-12)
         e_prev = e
+
+
+def test_energy_function_is_the_weighted_norm():
+    """elastic.energy equals 1/2 <Q, P~^{-1} Q>_H with the compliance applied
+    as an explicit 6x6 solve per node (independent of the closed form used in
+    elastic.energy)."""
+    blk = make_block(4, shape=(9, 10, 11), seed=5)
+    Q = W.random_state(blk.shape, 6)
+    m = blk.mat
+    w = blk.norm_weights() * blk.J
+    want = 0.0
+    for idx in np.ndindex(*blk.shape):
+        C = np.zeros((6, 6))
+        C[:3, :3] = m["lam"][idx]
+        for k in range(3):
+            C[k, k] += 2 * m["mu"][idx]
+        for k in range(3, 6):
+            C[k, k] = m["mu"][idx]
+        sig = Q[3:9][(slice(None),) + idx]
+        v = Q[0:3][(slice(None),) + idx]
+        want += 0.5 * w[idx] * (m["rho"][idx] * v @ v + sig @ np.linalg.solve(C, sig))
+    assert abs(E.energy(blk, Q) - want) <= 1e-12 * want
+
+
+def test_run_records_receivers_and_matches_manual_stepping():
+    wl = W.cube_pulse(n=9)
+    blk = E.Block(wl["xyz"], 4).set_material(wl["rho"], wl["cp"], wl["cs"])
+    rec = np.array([[1, 2, 3], [8, 0, 8], [4, 4, 4]])
+    Q, t, tr = E.run(blk, wl["Q0"], 3, wl["dt"], wl["gamma"], receivers=rec)
+    from oracle import lsrk
+    Qm = wl["Q0"].copy()
+    d = np.zeros_like(Qm)
+    for n in range(3):
+        lsrk.step(Qm, d, n * wl["dt"], wl["dt"], lambda q, tt: E.rhs(blk, q, tt, wl["gamma"]))
+        for r, (i, j, k) in enumerate(rec):
+            assert np.array_equal(tr[n, r], Qm[0:3, k, j, i])
+    assert np.array_equal(Q, Qm)
+    assert abs(t - 3 * wl["dt"]) < 1e-15
