@@ -100,6 +100,17 @@ struct Arr<T, false> {
   __device__ __forceinline__ void st(int c, unsigned off, T v) const { stf(p + c * field, off, v); }
 };
 
+// Flux e . sigma_i for the three components i, with e = (m0, m1, m2) a metric
+// row: explicit fused multiply-adds in a fixed order, so that every site that
+// forms the flux of a node (own point, halo point, s-queue) rounds identically
+// and results do not depend on the tiling.
+template <typename T>
+__device__ __forceinline__ void flux3(T m0, T m1, T m2, T sxx, T syy, T szz, T sxy, T sxz, T syz, T f[3]) {
+  f[0] = fma(m2, sxz, fma(m1, sxy, m0 * sxx));
+  f[1] = fma(m2, syz, fma(m1, syy, m0 * sxy));
+  f[2] = fma(m2, szz, fma(m1, syz, m0 * sxz));
+}
+
 // ---------------------------------------------------------------------------
 // boundary penalty at one face node, accumulated into rate[9]
 template <typename T>
@@ -231,9 +242,7 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
     const T m0 = gc.ld(6, o), m1 = gc.ld(7, o), m2 = gc.ld(8, o);
     const T sxx = gq.ld(3, o), syy = gq.ld(4, o), szz = gq.ld(5, o);
     const T sxy = gq.ld(6, o), sxz = gq.ld(7, o), syz = gq.ld(8, o);
-    f[0] = m0 * sxx + m1 * sxy + m2 * sxz;
-    f[1] = m0 * sxy + m1 * syy + m2 * syz;
-    f[2] = m0 * sxz + m1 * syz + m2 * szz;
+    flux3(m0, m1, m2, sxx, syy, szz, sxy, sxz, syz, f);
   };
   // ring slot of plane k (k >= -Q)
   auto slot = [&](int k) { return (k + 7 * QD) % QD; };
@@ -275,79 +284,129 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
   const T* __restrict__ ytab = tab + ((j < M) ? 0 : 2 * TABN);
   const int ncol = A.ncol;
 
+  // prefetch registers: everything plane a needs from memory (own sigma, M,
+  // material, Runge-Kutta register; the y-halo and x-halo points of the
+  // thread), loaded one plane ahead so that the loads of plane a+1 overlap
+  // the arithmetic of plane a
+  T p_sg[6], p_m[9], p_mat[3], p_dq[9], p_hy[12], p_hx[12];
+  const bool rdq = A.read_dq != 0;
+  auto load_plane = [&](int a) {
+    const unsigned pa = (unsigned)a * plane;
+    const unsigned o = pa + col;
+    if (ing) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) p_sg[c] = gq.ld(3 + c, o);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) p_m[c] = gc.ld(c, o);
+    }
+    if (act) {
+#pragma unroll
+      for (int c = 6; c < 9; ++c) p_m[c] = gc.ld(c, o);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p_mat[c] = gc.ld(9 + c, o);
+      if (rdq) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) p_dq[c] = gd.ld(c, o);
+      }
+    }
+    if (yh_in) {
+      const unsigned oh = pa + yh_col;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) p_hy[c] = gq.ld(c, oh);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p_hy[9 + c] = gc.ld(3 + c, oh);
+    }
+    if (xh_in) {
+      const unsigned oh = pa + xh_col;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) p_hx[c] = gq.ld(c, oh);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p_hx[9 + c] = gc.ld(c, oh);
+    }
+  };
+#pragma unroll
+  for (int c = 0; c < 6; ++c) p_sg[c] = T(0);
+#pragma unroll
+  for (int c = 0; c < 9; ++c) { p_m[c] = T(0); p_dq[c] = T(0); }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) p_mat[c] = T(0);
+  load_plane(z0);
+
   for (int a = z0; a < z1; ++a) {
     const unsigned pa = (unsigned)a * plane;
     const unsigned o = pa + col;
-    // ---------------- phase 1
-    T sg[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-    T mq[3] = {T(0), T(0), T(0)}, mr[3] = {T(0), T(0), T(0)};
-    T lead_v[3] = {T(0), T(0), T(0)}, lead_f[3] = {T(0), T(0), T(0)};
+    // ---------------- phase 1: stage plane a in LDS from the prefetched registers
+    T sg[6], mq[3], mr[3], ms[3], dqo[9];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sg[c] = p_sg[c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { mq[c] = p_m[c]; mr[c] = p_m[3 + c]; ms[c] = p_m[6 + c]; }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) dqo[c] = p_dq[c];
+    const T lamJ = p_mat[0], muJ = p_mat[1], rJ = p_mat[2];
     if (ing) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) sg[c] = gq.ld(3 + c, o);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) { mq[c] = gc.ld(c, o); mr[c] = gc.ld(3 + c, o); }
       lv[0 * VX * VY + vme] = vq[0][R];
       lv[1 * VX * VY + vme] = vq[1][R];
       lv[2 * VX * VY + vme] = vq[2][R];
-      lq[0 * QX * TY + qme] = mq[0] * sg[0] + mq[1] * sg[3] + mq[2] * sg[4];
-      lq[1 * QX * TY + qme] = mq[0] * sg[3] + mq[1] * sg[1] + mq[2] * sg[5];
-      lq[2 * QX * TY + qme] = mq[0] * sg[4] + mq[1] * sg[5] + mq[2] * sg[2];
-      lr[0 * RX * VY + rme] = mr[0] * sg[0] + mr[1] * sg[3] + mr[2] * sg[4];
-      lr[1 * RX * VY + rme] = mr[0] * sg[3] + mr[1] * sg[1] + mr[2] * sg[5];
-      lr[2 * RX * VY + rme] = mr[0] * sg[4] + mr[1] * sg[5] + mr[2] * sg[2];
-      const int kv = a + 1 + Q;
-      if (kv < ns) {
-        const unsigned ov = (unsigned)kv * plane + col;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) lead_v[c] = gq.ld(c, ov);
-      }
-      // the lead plane's ring slot is still read in phase 2 (plane a - Q):
-      // keep its flux in registers until the queue advance
-      const int kf = a + 1 + R;
-      if (kf < ns) sflux((unsigned)kf * plane + col, lead_f);
+      T f[3];
+      flux3(mq[0], mq[1], mq[2], sg[0], sg[1], sg[2], sg[3], sg[4], sg[5], f);
+      lq[0 * QX * TY + qme] = f[0];
+      lq[1 * QX * TY + qme] = f[1];
+      lq[2 * QX * TY + qme] = f[2];
+      flux3(mr[0], mr[1], mr[2], sg[0], sg[1], sg[2], sg[3], sg[4], sg[5], f);
+      lr[0 * RX * VY + rme] = f[0];
+      lr[1 * RX * VY + rme] = f[1];
+      lr[2 * RX * VY + rme] = f[2];
     }
-    if (yh_in) {  // v and r-flux of a y-halo point
-      const unsigned oh = pa + yh_col;
-      T h[12];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) h[c] = gq.ld(c, oh);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) h[9 + c] = gc.ld(3 + c, oh);
+    if (yh_in) {  // v and r-flux of the y-halo point
+      const T* h = p_hy;
       const int wv = yh_ly * VX + (tid & 63) + H;
       const int wr = yh_ly * RX + (tid & 63);
       lv[0 * VX * VY + wv] = h[0];
       lv[1 * VX * VY + wv] = h[1];
       lv[2 * VX * VY + wv] = h[2];
-      lr[0 * RX * VY + wr] = h[9] * h[3] + h[10] * h[6] + h[11] * h[7];
-      lr[1 * RX * VY + wr] = h[9] * h[6] + h[10] * h[4] + h[11] * h[8];
-      lr[2 * RX * VY + wr] = h[9] * h[7] + h[10] * h[8] + h[11] * h[5];
+      T f[3];
+      flux3(h[9], h[10], h[11], h[3], h[4], h[5], h[6], h[7], h[8], f);
+      lr[0 * RX * VY + wr] = f[0];
+      lr[1 * RX * VY + wr] = f[1];
+      lr[2 * RX * VY + wr] = f[2];
     }
-    if (xh_in) {  // v and q-flux of an x-halo point
-      const unsigned oh = pa + xh_col;
-      T h[12];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) h[c] = gq.ld(c, oh);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) h[9 + c] = gc.ld(c, oh);
+    if (xh_in) {  // v and q-flux of the x-halo point
+      const T* h = p_hx;
       const int wv = (xh_r + H) * VX + xh_lx;
       const int wq = xh_r * QX + xh_lx;
       lv[0 * VX * VY + wv] = h[0];
       lv[1 * VX * VY + wv] = h[1];
       lv[2 * VX * VY + wv] = h[2];
-      lq[0 * QX * TY + wq] = h[9] * h[3] + h[10] * h[6] + h[11] * h[7];
-      lq[1 * QX * TY + wq] = h[9] * h[6] + h[10] * h[4] + h[11] * h[8];
-      lq[2 * QX * TY + wq] = h[9] * h[7] + h[10] * h[8] + h[11] * h[5];
+      T f[3];
+      flux3(h[9], h[10], h[11], h[3], h[4], h[5], h[6], h[7], h[8], f);
+      lq[0 * QX * TY + wq] = f[0];
+      lq[1 * QX * TY + wq] = f[1];
+      lq[2 * QX * TY + wq] = f[2];
     }
     __syncthreads();
 
+    // s-queue lead planes, then the prefetch of plane a+1.  The lead values
+    // stay raw until the end of the plane: forming the flux here would make
+    // the compiler wait for every load issued so far (vmcnt retires in order).
+    // Plane indices are clamped so that the loads need no branch; clamped
+    // values belong to planes >= ns, which no interior plane reads.
+    T lead_v[3], lead_raw[9];
+    {
+      const unsigned cl = ing ? col : 0u;
+      const unsigned ov = (unsigned)min(a + 1 + Q, ns - 1) * plane + cl;
+      const unsigned of = (unsigned)min(a + 1 + R, ns - 1) * plane + cl;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) lead_v[c] = gq.ld(c, ov);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) lead_raw[c] = gq.ld(3 + c, of);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) lead_raw[6 + c] = gc.ld(6 + c, of);
+    }
+    if (a + 1 < z1) load_plane(a + 1);
+
     // ---------------- phase 2
     if (act) {
-      T ms[3], dqo[9];
-      for (int c = 0; c < 3; ++c) ms[c] = gc.ld(6 + c, o);
-      const T lamJ = gc.ld(9, o), muJ = gc.ld(10, o), rJ = gc.ld(11, o);
-#pragma unroll
-      for (int c = 0; c < 9; ++c) dqo[c] = A.read_dq ? gd.ld(c, o) : T(0);
       T u[3][3];   // u[xi][c] = D+_xi v_c
       T dv[3];     // sum_xi D-_xi F_xi,c
       // q direction
@@ -521,10 +580,13 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
       for (int c = 0; c < 3; ++c) vq[c][s] = vq[c][s + 1];
 #pragma unroll
     for (int c = 0; c < 3; ++c) vq[c][QD - 1] = lead_v[c];
-    if (ing) {
+    {
+      const T* r = lead_raw;  // sigma (6), M_s (3) of plane a + 1 + R
+      T f[3];
+      flux3(r[6], r[7], r[8], r[0], r[1], r[2], r[3], r[4], r[5], f);
       const int sl = slot(a + 1 + R);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ring[(sl * 3 + c) * NT + tid] = lead_f[c];
+      for (int c = 0; c < 3; ++c) ring[(sl * 3 + c) * NT + tid] = f[c];
     }
   }
 }

