@@ -119,7 +119,9 @@ int check_dims(int nq, int nr, int ns, int order, int dtype) {
 void layout(sbp_ctx* h) {
   const int es = h->esize;
   const Geometry& g = h->g;
-  h->px = (g.nq + 15) / 16 * 16;
+  // rows start on 128-byte lines (the memory request size)
+  const int line = 128 / es;
+  h->px = (g.nq + line - 1) / line * line;
   h->plane = (std::size_t)h->px * g.nr;
   h->field = h->plane * g.ns;
   std::size_t o = 0;
@@ -306,10 +308,29 @@ std::vector<int> tile_bounds(int N, int W, int m) {
   return b;
 }
 
+// split of [0, N) along q into tiles of width <= 64 whose starts are
+// multiples of `align` points (128-byte lines), the first and last tile
+// holding at least m points
+std::vector<int> tile_bounds_aligned(int N, int align, int m) {
+  std::vector<int> b{0};
+  while (N - b.back() > 64) b.push_back(b.back() + 64);
+  b.push_back(N);
+  // a last tile narrower than m: move its start back by one line at a time
+  while (b.size() > 2 && b[b.size() - 1] - b[b.size() - 2] < m) {
+    const int s = b[b.size() - 2] - align;
+    if (s <= b[b.size() - 3]) break;
+    b[b.size() - 2] = s;
+  }
+  bool ok = b.size() >= 2;
+  for (std::size_t t = 0; t + 1 < b.size(); ++t) ok = ok && b[t + 1] - b[t] <= 64 && b[t + 1] > b[t];
+  ok = ok && (b.size() == 2 || (b[1] - b[0] >= m && b[b.size() - 1] - b[b.size() - 2] >= m));
+  return ok ? b : tile_bounds(N, 64, m);
+}
+
 int prepare_bounds(sbp_ctx* h) {
   if (!h->bounds_dirty) return SBP_OK;
   const Geometry& g = h->g;
-  std::vector<int> xb = tile_bounds(g.nq, 64, h->cl.m);
+  std::vector<int> xb = tile_bounds_aligned(g.nq, 128 / h->esize, h->cl.m);
   std::vector<int> yb = tile_bounds(g.nr, h->ty, h->cl.m);
   h->nxt = (int)xb.size() - 1;
   h->nyt = (int)yb.size() - 1;
