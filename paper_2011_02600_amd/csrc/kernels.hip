@@ -63,7 +63,10 @@ __device__ __forceinline__ void stf(T* base, unsigned off, T v) {
 // Field array accessor: BUF = true uses a buffer resource (one descriptor per
 // array, the field offset in a scalar register, the element offset as a
 // 32-bit vector offset; the array must be smaller than 4 GiB); BUF = false
-// uses plain pointers.
+// uses plain pointers.  ldn / st mark the access non-temporal (cache policy
+// bit NT): data that no other block reads during the launch (the Runge-Kutta
+// register, the material, every store) then does not push the halo lines
+// that neighbouring tiles are about to read out of L2.
 template <typename T, bool BUF>
 struct Arr;
 
@@ -74,19 +77,23 @@ struct Arr<T, true> {
   __device__ Arr(const T* p, std::size_t field)
       : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(p), (short)0, -1, 0x00020000)),
         fbytes((unsigned)(field * sizeof(T))) {}
-  __device__ __forceinline__ T ld(int c, unsigned off) const {
+  static constexpr int kNT = 2;  // cache policy: non-temporal
+  template <int POL = 0>
+  __device__ __forceinline__ T ldp(int c, unsigned off) const {
     if constexpr (sizeof(T) == 4) {
-      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(off * 4u), (int)(c * fbytes), 0));
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)(off * 4u), (int)(c * fbytes), POL));
     } else {
-      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(off * 8u), (int)(c * fbytes), 0));
+      return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)(off * 8u), (int)(c * fbytes), POL));
     }
   }
+  __device__ __forceinline__ T ld(int c, unsigned off) const { return ldp<0>(c, off); }
+  __device__ __forceinline__ T ldn(int c, unsigned off) const { return ldp<kNT>(c, off); }
   __device__ __forceinline__ void st(int c, unsigned off, T v) const {
     if constexpr (sizeof(T) == 4) {
-      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)(off * 4u), (int)(c * fbytes), 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)(off * 4u), (int)(c * fbytes), kNT);
     } else {
       using u2 = unsigned __attribute__((ext_vector_type(2)));
-      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)(off * 8u), (int)(c * fbytes), 0);
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)(off * 8u), (int)(c * fbytes), kNT);
     }
   }
 };
@@ -97,6 +104,7 @@ struct Arr<T, false> {
   std::size_t field;
   __device__ Arr(const T* p_, std::size_t f) : p(const_cast<T*>(p_)), field(f) {}
   __device__ __forceinline__ T ld(int c, unsigned off) const { return ldf(p + c * field, off); }
+  __device__ __forceinline__ T ldn(int c, unsigned off) const { return ldf(p + c * field, off); }
   __device__ __forceinline__ void st(int c, unsigned off, T v) const { stf(p + c * field, off, v); }
 };
 
@@ -114,11 +122,10 @@ __device__ __forceinline__ void flux3(T m0, T m1, T m2, T sxx, T syy, T szz, T s
 // ---------------------------------------------------------------------------
 // boundary penalty at one face node, accumulated into rate[9]
 template <typename T>
-__device__ __forceinline__ void face_penalty(const T* __restrict__ fc, std::size_t fstride,
-                                             T gamma, T eps, bool traction, const T v[3],
-                                             const T sg[6], T rate[9]) {
-  const T nx = fc[FN_X * fstride], ny = fc[FN_Y * fstride], nz = fc[FN_Z * fstride];
-  const T kr = fc[F_KR * fstride];
+__device__ __forceinline__ void face_penalty(const T fc[kNumFaceCoef], T gamma, T eps, bool traction,
+                                             const T v[3], const T sg[6], T rate[9]) {
+  const T nx = fc[FN_X], ny = fc[FN_Y], nz = fc[FN_Z];
+  const T kr = fc[F_KR];
   // traction T = sigma n
   const T Tx = sg[0] * nx + sg[3] * ny + sg[4] * nz;
   const T Ty = sg[3] * nx + sg[1] * ny + sg[5] * nz;
@@ -129,9 +136,9 @@ __device__ __forceinline__ void face_penalty(const T* __restrict__ fc, std::size
     rate[2] -= eps * kr * Tz;
     return;
   }
-  const T zp = fc[F_ZP * fstride], zs = fc[F_ZS * fstride];
-  const T izp = fc[F_IZP * fstride], izs = fc[F_IZS * fstride];
-  const T kl = fc[F_KL * fstride], km = fc[F_KM * fstride];
+  const T zp = fc[F_ZP], zs = fc[F_ZS];
+  const T izp = fc[F_IZP], izs = fc[F_IZS];
+  const T kl = fc[F_KL], km = fc[F_KM];
   const T vn = v[0] * nx + v[1] * ny + v[2] * nz;
   const T Tn = Tx * nx + Ty * ny + Tz * nz;
   const T cv = T(0.5) * (T(1) - gamma);
@@ -193,6 +200,26 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
   __shared__ T lq[3 * QX * TY];
   __shared__ T lr[3 * RX * VY];
   __shared__ T ring[QD * 3 * NT];
+  // sigma (6) and M_s (3) of planes a .. a+R, read once from memory as the
+  // s-flux lead and kept until the plane is the output plane (when the LDS
+  // budget allows it; otherwise plane a reloads them)
+  constexpr int SD = R + 1;
+  constexpr std::size_t kBaseLds =
+      sizeof(T) * (3 * VX * VY + 3 * QX * TY + 3 * RX * VY + QD * 3 * NT);
+  constexpr bool SR = kBaseLds + sizeof(T) * SD * 9 * NT <= 160 * 1024;
+  __shared__ T sring[SR ? SD * 9 * NT : 1];
+  // closure coefficients (rows of D+, D-, and their mirror images)
+  __shared__ T ltab[kClosureTab * TABN];
+  // penalty coefficients of the tile's q faces (TY rows) and r faces (64
+  // columns) for the current plane, loaded one plane ahead like the field
+  // data (a wait for a load issued later than the prefetch would also wait
+  // for the prefetch); kept in LDS when the budget allows it
+  constexpr int NFQ = kNumFaceCoef * TY, NFR = kNumFaceCoef * 64;
+  constexpr int NFE = 2 * NFQ + 2 * NFR;
+  constexpr bool FL = kBaseLds + (SR ? sizeof(T) * SD * 9 * NT : 0) +
+                          sizeof(T) * (kClosureTab * TABN + NFE) <= 160 * 1024;
+  constexpr int KF = FL ? (NFE + NT - 1) / NT : 1;
+  __shared__ T lface[FL ? NFE : 1];
 
   // XCD-aware tile order: consecutive tiles land on the same XCD
   const int per = gridDim.x >> 3;
@@ -219,7 +246,7 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
   const unsigned col = (unsigned)j * px + (unsigned)i;
 
   const Arr<T, BUF> gq(A.qin, field), gc(A.coef, field), gd(A.dq, field), go(A.qout, field);
-  const T* __restrict__ tab = A.tab;
+  for (int e = threadIdx.y * 64 + threadIdx.x; e < kClosureTab * TABN; e += NT) ltab[e] = A.tab[e];
 
   // y halo: rows y0-H..y0-1 and y0+TY..y0+TY+H-1, columns x0..x0+63
   const int yh_r = tid >> 6;
@@ -228,6 +255,11 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
   const bool yh_in = tid < NYH && yh_gx < nq && yh_gy >= 0 && yh_gy < nr;
   const int yh_ly = (yh_r < H) ? yh_r : TY + yh_r;   // row in the v / F_r windows
   const unsigned yh_col = yh_in ? (unsigned)yh_gy * px + (unsigned)yh_gx : 0u;
+  // D+ reads v at R rows below and Q rows above a node, D- reads the flux at
+  // Q below and R above: only those halo rows are loaded.  The last tile
+  // along r keeps every lower v row, which its boundary closure rows read.
+  const bool yh_v = yh_in && (yh_r >= H - R || y1 == nr);
+  const bool yh_f = yh_in && yh_r < H + R;
   // x halo: columns x0-H..x0-1 and x0+64..x0+64+H-1, rows y0..y0+TY-1
   const int xh_c = tid / TY;
   const int xh_r = tid - xh_c * TY;
@@ -236,6 +268,8 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
   const bool xh_in = tid < NXH && xh_gx >= 0 && xh_gx < nq && xh_gy < nr;
   const int xh_lx = (xh_c < H) ? xh_c : 64 + xh_c;  // column in the v / F_q windows
   const unsigned xh_col = xh_in ? (unsigned)xh_gy * px + (unsigned)xh_gx : 0u;
+  // waves holding x-halo lanes (a wave-uniform condition)
+  const bool xh_wave = __builtin_amdgcn_readfirstlane(ty) * 64 < NXH;
 
   // s-flux F_s,i = sum_c M[s][c] sigma_ic
   auto sflux = [&](unsigned o, T f[3]) {
@@ -266,7 +300,19 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
     for (int s = 0; s < QD; ++s) {
       const int kf = z0 - Q + s;
       T f[3] = {T(0), T(0), T(0)};
-      if (kf >= 0 && kf < ns) sflux((unsigned)kf * plane + col, f);
+      if (kf >= 0 && kf < ns) {
+        const unsigned o = (unsigned)kf * plane + col;
+        T r[9];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) r[c] = gq.ld(3 + c, o);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r[6 + c] = gc.ld(6 + c, o);
+        flux3(r[6], r[7], r[8], r[0], r[1], r[2], r[3], r[4], r[5], f);
+        if (SR && kf >= z0) {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) sring[((kf % SD) * 9 + c) * NT + tid] = r[c];
+        }
+      }
 #pragma unroll
       for (int c = 0; c < 3; ++c) ring[(slot(kf) * 3 + c) * NT + tid] = f[c];
     }
@@ -280,69 +326,139 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
   const bool yin = j >= M && j < nr - M;
   const int xrow = (i < M) ? i : nq - 1 - i;
   const int yrow = (j < M) ? j : nr - 1 - j;
-  const T* __restrict__ xtab = tab + ((i < M) ? 0 : 2 * TABN);
-  const T* __restrict__ ytab = tab + ((j < M) ? 0 : 2 * TABN);
+  const int xtab = (i < M) ? 0 : 2 * TABN;   // closure rows in ltab
+  const int ytab = (j < M) ? 0 : 2 * TABN;
   const int ncol = A.ncol;
 
   // prefetch registers: everything plane a needs from memory (own sigma, M,
   // material, Runge-Kutta register; the y-halo and x-halo points of the
   // thread), loaded one plane ahead so that the loads of plane a+1 overlap
   // the arithmetic of plane a
-  T p_sg[6], p_m[9], p_mat[3], p_dq[9], p_hy[12], p_hx[12];
+  constexpr int NSG = SR ? 1 : 6, NMS = SR ? 6 : 9;
+  T p_sg[NSG], p_m[NMS], p_mat[3], p_dq[9], p_hy[12], p_hx[12];
   const bool rdq = A.read_dq != 0;
+  // penalty coefficients of the tile's faces: lface entry e is face f,
+  // coefficient k, position pos along the face (row offset from y0 on the q
+  // faces, column offset from x0 on the r faces)
+  const bool fq0 = x0 == 0, fq1 = x1 == nq, fr0 = y0 == 0, fr1 = y1 == nr;
+  const bool anyface = FL && (fq0 || fq1 || fr0 || fr1);
+  auto face_src = [&](int e, int p, std::size_t& src) -> bool {
+    if (e < 2 * NFQ) {
+      const int f = e / NFQ, rem = e - f * NFQ, k = rem / TY, pos = rem - k * TY;
+      const int jj = y0 + pos;
+      if (!(f == 0 ? fq0 : fq1) || jj >= nr) return false;
+      const std::size_t fo = f == 0 ? A.face_off[0] : A.face_off[1];
+      const std::size_t fn = f == 0 ? A.face_n[0] : A.face_n[1];
+      src = fo + (std::size_t)p * nr + jj + (std::size_t)k * fn;
+      return true;
+    }
+    if (e < NFE) {
+      const int e2 = e - 2 * NFQ, g = e2 / NFR, rem = e2 - g * NFR, k = rem / 64, pos = rem - k * 64;
+      const int ii = x0 + pos;
+      if (!(g == 0 ? fr0 : fr1) || ii >= nq) return false;
+      const std::size_t fo = g == 0 ? A.face_off[2] : A.face_off[3];
+      const std::size_t fn = g == 0 ? A.face_n[2] : A.face_n[3];
+      src = fo + (std::size_t)p * nq + ii + (std::size_t)k * fn;
+      return true;
+    }
+    return false;
+  };
+  T p_face[KF];
+#pragma unroll
+  for (int u = 0; u < KF; ++u) p_face[u] = T(0);
   auto load_plane = [&](int a) {
     const unsigned pa = (unsigned)a * plane;
-    const unsigned o = pa + col;
-    if (ing) {
+    // Every lane loads; a lane that needs no value reads element 0 of the
+    // plane (or of the array).  Loads under a mask or a branch would make the
+    // compiler merge old and new register values, and the merge waits for
+    // the loads in flight.
+    if constexpr (FL) {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) p_sg[c] = gq.ld(3 + c, o);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) p_m[c] = gc.ld(c, o);
-    }
-    if (act) {
-#pragma unroll
-      for (int c = 6; c < 9; ++c) p_m[c] = gc.ld(c, o);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) p_mat[c] = gc.ld(9 + c, o);
-      if (rdq) {
-#pragma unroll
-        for (int c = 0; c < 9; ++c) p_dq[c] = gd.ld(c, o);
+      for (int u = 0; u < KF; ++u) {
+        std::size_t src = 0;
+        const bool need = anyface && face_src(tid + u * NT, a, src);
+        p_face[u] = A.face[need ? src : 0];
       }
     }
-    if (yh_in) {
-      const unsigned oh = pa + yh_col;
+    const unsigned oi = pa + (ing ? col : 0u);
+    const unsigned oa = pa + (act ? col : 0u);
+    if constexpr (!SR) {
 #pragma unroll
-      for (int c = 0; c < 9; ++c) p_hy[c] = gq.ld(c, oh);
+      for (int c = 0; c < 6; ++c) p_sg[c] = gq.ld(3 + c, oi);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) p_hy[9 + c] = gc.ld(3 + c, oh);
+      for (int c = 6; c < 9; ++c) p_m[c] = gc.ld(c, oa);
     }
-    if (xh_in) {
-      const unsigned oh = pa + xh_col;
 #pragma unroll
-      for (int c = 0; c < 9; ++c) p_hx[c] = gq.ld(c, oh);
+    for (int c = 0; c < 6; ++c) p_m[c] = gc.ld(c, oi);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) p_hx[9 + c] = gc.ld(c, oh);
+    for (int c = 0; c < 3; ++c) p_mat[c] = gc.ldn(9 + c, oa);
+    const unsigned od = rdq ? oa : 0u;   // unused (and masked below) in the first stage
+#pragma unroll
+    for (int c = 0; c < 9; ++c) p_dq[c] = gd.ldn(c, od);
+    const unsigned ohv = pa + (yh_v ? yh_col : 0u);
+    const unsigned ohf = pa + (yh_f ? yh_col : 0u);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p_hy[c] = gq.ld(c, ohv);
+#pragma unroll
+    for (int c = 3; c < 9; ++c) p_hy[c] = gq.ld(c, ohf);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p_hy[9 + c] = gc.ld(3 + c, ohf);
+    if (xh_wave) {
+      const unsigned ox = pa + xh_col;
+#pragma unroll
+      for (int c = 0; c < 9; ++c) p_hx[c] = gq.ld(c, ox);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p_hx[9 + c] = gc.ld(c, ox);
     }
   };
 #pragma unroll
-  for (int c = 0; c < 6; ++c) p_sg[c] = T(0);
+  for (int c = 0; c < NSG; ++c) p_sg[c] = T(0);
 #pragma unroll
-  for (int c = 0; c < 9; ++c) { p_m[c] = T(0); p_dq[c] = T(0); }
+  for (int c = 0; c < NMS; ++c) p_m[c] = T(0);
+#pragma unroll
+  for (int c = 0; c < 9; ++c) p_dq[c] = T(0);
 #pragma unroll
   for (int c = 0; c < 3; ++c) p_mat[c] = T(0);
   load_plane(z0);
+
+  // results of the previous plane, stored after the next plane's loads have
+  // been issued: loads and stores share one counter, and a wait for a load
+  // while stores are in flight waits for the stores as well, so stores issued
+  // at the end of a plane would put one write round trip on every plane
+  T st_d[9], st_q[9];
+  unsigned st_o = 0;
+  bool st_pend = false;
+  auto flush_stores = [&]() {
+    if (st_pend && act) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        gd.st(c, st_o, st_d[c]);
+        go.st(c, st_o, st_q[c]);
+      }
+    }
+  };
 
   for (int a = z0; a < z1; ++a) {
     const unsigned pa = (unsigned)a * plane;
     const unsigned o = pa + col;
     // ---------------- phase 1: stage plane a in LDS from the prefetched registers
     T sg[6], mq[3], mr[3], ms[3], dqo[9];
+    if constexpr (SR) {
+      const int sl = a % SD;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) sg[c] = p_sg[c];
+      for (int c = 0; c < 6; ++c) sg[c] = sring[(sl * 9 + c) * NT + tid];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) { mq[c] = p_m[c]; mr[c] = p_m[3 + c]; ms[c] = p_m[6 + c]; }
+      for (int c = 0; c < 3; ++c) ms[c] = sring[(sl * 9 + 6 + c) * NT + tid];
+    } else {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) dqo[c] = p_dq[c];
+      for (int c = 0; c < 6; ++c) sg[c] = p_sg[c];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) ms[c] = p_m[6 + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { mq[c] = p_m[c]; mr[c] = p_m[3 + c]; }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) dqo[c] = rdq ? p_dq[c] : T(0);
     const T lamJ = p_mat[0], muJ = p_mat[1], rJ = p_mat[2];
     if (ing) {
       lv[0 * VX * VY + vme] = vq[0][R];
@@ -358,13 +474,16 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
       lr[1 * RX * VY + rme] = f[1];
       lr[2 * RX * VY + rme] = f[2];
     }
-    if (yh_in) {  // v and r-flux of the y-halo point
+    if (yh_v) {  // v of the y-halo point
       const T* h = p_hy;
       const int wv = yh_ly * VX + (tid & 63) + H;
-      const int wr = yh_ly * RX + (tid & 63);
       lv[0 * VX * VY + wv] = h[0];
       lv[1 * VX * VY + wv] = h[1];
       lv[2 * VX * VY + wv] = h[2];
+    }
+    if (yh_f) {  // r-flux of the y-halo point
+      const T* h = p_hy;
+      const int wr = yh_ly * RX + (tid & 63);
       T f[3];
       flux3(h[9], h[10], h[11], h[3], h[4], h[5], h[6], h[7], h[8], f);
       lr[0 * RX * VY + wr] = f[0];
@@ -383,6 +502,15 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
       lq[0 * QX * TY + wq] = f[0];
       lq[1 * QX * TY + wq] = f[1];
       lq[2 * QX * TY + wq] = f[2];
+    }
+    if constexpr (FL) {
+      if (anyface) {
+#pragma unroll
+        for (int u = 0; u < KF; ++u) {
+          const int e = tid + u * NT;
+          if (e < NFE) lface[e] = p_face[u];
+        }
+      }
     }
     __syncthreads();
 
@@ -403,7 +531,8 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
 #pragma unroll
       for (int c = 0; c < 3; ++c) lead_raw[6 + c] = gc.ld(6 + c, of);
     }
-    if (a + 1 < z1) load_plane(a + 1);
+    load_plane(min(a + 1, ns - 1));   // the last plane's prefetch is unused
+    flush_stores();                   // after every load of the plane
 
     // ---------------- phase 2
     if (act) {
@@ -429,8 +558,8 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
         const int gq = ty * QX + H - x0 + (left ? 0 : nq - 1);
         const int step = left ? 1 : -1;
         for (int cc = 0; cc < ncol; ++cc) {
-          const T cp = xtab[xrow * kMaxCols + cc];
-          const T cm = xtab[TABN + xrow * kMaxCols + cc];
+          const T cp = ltab[xtab + xrow * kMaxCols + cc];
+          const T cm = ltab[xtab + TABN + xrow * kMaxCols + cc];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             sp[c] += cp * lv[c * VX * VY + gv + step * cc];
@@ -462,8 +591,8 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
         const int rowv = H - y0 + (left ? 0 : nr - 1);
         const int stepr = left ? 1 : -1;
         for (int cc = 0; cc < ncol; ++cc) {
-          const T cp = ytab[yrow * kMaxCols + cc];
-          const T cm = ytab[TABN + yrow * kMaxCols + cc];
+          const T cp = ltab[ytab + yrow * kMaxCols + cc];
+          const T cm = ltab[ytab + TABN + yrow * kMaxCols + cc];
           const int rw = rowv + stepr * cc;
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
@@ -496,15 +625,15 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
       } else {
         const bool left = a < M;
         const int row = left ? a : ns - 1 - a;
-        const T* __restrict__ zt = tab + (left ? 0 : 2 * TABN);
+        const int zt = left ? 0 : 2 * TABN;
         T sp[3] = {T(0), T(0), T(0)}, sm[3] = {T(0), T(0), T(0)};
         for (int cc = 0; cc < ncol; ++cc) {
           const int k = left ? cc : ns - 1 - cc;
           const unsigned ok = (unsigned)k * plane + col;
           T f[3];
           sflux(ok, f);
-          const T cp = zt[row * kMaxCols + cc];
-          const T cm = zt[TABN + row * kMaxCols + cc];
+          const T cp = ltab[zt + row * kMaxCols + cc];
+          const T cm = ltab[zt + TABN + row * kMaxCols + cc];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             sp[c] += cp * gq.ld(c, ok);
@@ -540,24 +669,53 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
 
       // boundary penalties (faces q0, q1, r0, r1, s0, s1)
       if (i == 0 || i == nq - 1 || j == 0 || j == nr - 1 || a == 0 || a == ns - 1) {
-        if (i == 0)
-          face_penalty(A.face + A.face_off[0] + ((std::size_t)a * nr + j), A.face_n[0], A.gamma[0],
-                       T(-1), A.traction[0], v, sg, rate);
-        if (i == nq - 1)
-          face_penalty(A.face + A.face_off[1] + ((std::size_t)a * nr + j), A.face_n[1], A.gamma[1],
-                       T(1), A.traction[1], v, sg, rate);
-        if (j == 0)
-          face_penalty(A.face + A.face_off[2] + ((std::size_t)a * nq + i), A.face_n[2], A.gamma[2],
-                       T(-1), A.traction[2], v, sg, rate);
-        if (j == nr - 1)
-          face_penalty(A.face + A.face_off[3] + ((std::size_t)a * nq + i), A.face_n[3], A.gamma[3],
-                       T(1), A.traction[3], v, sg, rate);
-        if (a == 0)
-          face_penalty(A.face + A.face_off[4] + ((std::size_t)j * nq + i), A.face_n[4], A.gamma[4],
-                       T(-1), A.traction[4], v, sg, rate);
-        if (a == ns - 1)
-          face_penalty(A.face + A.face_off[5] + ((std::size_t)j * nq + i), A.face_n[5], A.gamma[5],
-                       T(1), A.traction[5], v, sg, rate);
+        T fc[kNumFaceCoef];
+        // coefficients of face f at in-face index idx, from global memory
+        auto face_global = [&](int f, std::size_t idx) {
+#pragma unroll
+          for (int k = 0; k < kNumFaceCoef; ++k) fc[k] = A.face[A.face_off[f] + idx + (std::size_t)k * A.face_n[f]];
+        };
+        // q face f (0 or 1) and r face f (2 or 3) of the current plane
+        auto face_q = [&](int f) {
+          if constexpr (FL) {
+#pragma unroll
+            for (int k = 0; k < kNumFaceCoef; ++k) fc[k] = lface[f * NFQ + k * TY + ty];
+          } else {
+            face_global(f, (std::size_t)a * nr + j);
+          }
+        };
+        auto face_r = [&](int f) {
+          if constexpr (FL) {
+#pragma unroll
+            for (int k = 0; k < kNumFaceCoef; ++k) fc[k] = lface[2 * NFQ + (f - 2) * NFR + k * 64 + tx];
+          } else {
+            face_global(f, (std::size_t)a * nq + i);
+          }
+        };
+        if (i == 0) {
+          face_q(0);
+          face_penalty(fc, A.gamma[0], T(-1), A.traction[0], v, sg, rate);
+        }
+        if (i == nq - 1) {
+          face_q(1);
+          face_penalty(fc, A.gamma[1], T(1), A.traction[1], v, sg, rate);
+        }
+        if (j == 0) {
+          face_r(2);
+          face_penalty(fc, A.gamma[2], T(-1), A.traction[2], v, sg, rate);
+        }
+        if (j == nr - 1) {
+          face_r(3);
+          face_penalty(fc, A.gamma[3], T(1), A.traction[3], v, sg, rate);
+        }
+        if (a == 0) {
+          face_global(4, (std::size_t)j * nq + i);
+          face_penalty(fc, A.gamma[4], T(-1), A.traction[4], v, sg, rate);
+        }
+        if (a == ns - 1) {
+          face_global(5, (std::size_t)j * nq + i);
+          face_penalty(fc, A.gamma[5], T(1), A.traction[5], v, sg, rate);
+        }
       }
 
       // Runge-Kutta stage update
@@ -565,11 +723,13 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
         const T d = dt * rate[c] + Ak * dqo[c];
-        gd.st(c, o, d);
         const T q0 = (c < 3) ? v[c] : sg[c - 3];
-        go.st(c, o, q0 + Bk * d);
+        st_d[c] = d;
+        st_q[c] = q0 + Bk * d;
       }
+      st_o = o;
     }
+    st_pend = true;
     __syncthreads();
 
     // advance the s queues to plane a + 1 (the ring slot of plane a - Q
@@ -587,8 +747,14 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
       const int sl = slot(a + 1 + R);
 #pragma unroll
       for (int c = 0; c < 3; ++c) ring[(sl * 3 + c) * NT + tid] = f[c];
+      if constexpr (SR) {  // plane a's slot is free now: it takes plane a + 1 + R
+        const int ss = (a + 1 + R) % SD;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) sring[(ss * 9 + c) * NT + tid] = r[c];
+      }
     }
   }
+  flush_stores();
 }
 
 // ---------------------------------------------------------------------------
