@@ -98,6 +98,7 @@ struct sbp_ctx {
   void* rec_out = nullptr;
   int ty = 8, zchunk = 0;
   int nxt = 0, nyt = 0, nzc = 0;
+  int ex = 0, ey = 0;   // last q column / last r row computed by the edge kernel
   bool bounds_dirty = true;
 };
 
@@ -330,19 +331,42 @@ std::vector<int> tile_bounds_aligned(int N, int align, int m) {
 int prepare_bounds(sbp_ctx* h) {
   if (!h->bounds_dirty) return SBP_OK;
   const Geometry& g = h->g;
-  std::vector<int> xb = tile_bounds_aligned(g.nq, 128 / h->esize, h->cl.m);
-  std::vector<int> yb = tile_bounds(g.nr, h->ty, h->cl.m);
+  const int line = 128 / h->esize;  // points per 128-byte line
+  // Grids of 64k + 1 points along q (more generally line * k + 1) and
+  // ty * k + 1 along r: the tiles cover [0, nq - 1) x [0, nr - 1) exactly and
+  // the edge kernel takes the last column and row, so that no tile is
+  // narrower than a line or shorter than ty.
+  h->ex = ((g.nq - 1) % line == 0 && g.nq - 1 >= 64) ? 1 : 0;
+  h->ey = ((g.nr - 1) % h->ty == 0 && g.nr - 1 >= 2 * h->ty) ? 1 : 0;
+  std::vector<int> xb = tile_bounds_aligned(g.nq - h->ex, line, h->cl.m);
+  std::vector<int> yb = tile_bounds(g.nr - h->ey, h->ty, h->cl.m);
   h->nxt = (int)xb.size() - 1;
   h->nyt = (int)yb.size() - 1;
   int zc = h->zchunk;
   if (zc <= 0) {
-    // one resident wave of blocks: two blocks of 8 rows (or one of 16) per
-    // compute unit on 256 compute units, split along s
-    const long long slots = h->ty == 8 ? 512 : 256;
+    // chunks along s: the s queues of a chunk start with r + q + 1 planes
+    // of warm-up, and the blocks run in waves of one block per compute unit;
+    // take the number of chunks that minimises waves x (planes + warm-up)
+    int cus = 256;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      int v = 0;
+      if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+    }
     const long long cols = (long long)h->nxt * h->nyt;
-    long long nz = std::max(1LL, slots / cols);
-    nz = std::min(nz, (long long)std::max(1, g.ns / 8));
-    zc = (int)((g.ns + nz - 1) / nz);
+    const int warm = h->cl.r + h->cl.q + 1;
+    const int nzmax = std::max(1, g.ns / 8);
+    long long best = -1;
+    int bestnz = 1;
+    for (int nz = 1; nz <= nzmax; ++nz) {
+      const long long waves = (cols * nz + cus - 1) / cus;
+      const long long cost = waves * ((g.ns + nz - 1) / nz + warm);
+      if (best < 0 || cost < best) {
+        best = cost;
+        bestnz = nz;
+      }
+    }
+    zc = (g.ns + bestnz - 1) / bestnz;
   }
   zc = std::max(1, std::min(zc, g.ns));
   h->nzc = (g.ns + zc - 1) / zc;
@@ -408,6 +432,7 @@ int run_stage(sbp_ctx* h, StageArgs<T>& a, int k, double dt, double tstage, bool
   a.Bk = rhs_only ? T(0) : (T)kRkB[k];
   a.dt = rhs_only ? T(1) : (T)dt;
   HIPCHK(launch_stage<T>(h->order, h->ty, a, h->stream));
+  if (h->ex || h->ey) HIPCHK(launch_edge<T>(h->order, a, h->ex, h->ey, h->stream));
   if (!h->src.empty()) {
     SourceArgs<T> s{};
     s.dq = dq;

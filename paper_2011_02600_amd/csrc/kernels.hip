@@ -166,6 +166,30 @@ __device__ __forceinline__ void face_penalty(const T fc[kNumFaceCoef], T gamma, 
 }
 
 // ---------------------------------------------------------------------------
+// pointwise part of the right-hand side at one node: stress rates from the
+// velocity derivatives u[xi][i] = D+_xi v_i (non-conservative metric form
+// and Hooke's law) and momentum rates from dv[i] = sum_xi D-_xi F_xi,i
+template <typename T>
+__device__ __forceinline__ void node_rates(const T u[3][3], const T dv[3], const T mq[3], const T mr[3],
+                                           const T ms[3], T lamJ, T muJ, T rJ, T rate[9]) {
+  T G[3][3];  // G[c][ii] = sum_xi M[xi][c] u[xi][ii]  (= J dv_ii/dx_c)
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii) G[c][ii] = mq[c] * u[0][ii] + mr[c] * u[1][ii] + ms[c] * u[2][ii];
+  const T div = G[0][0] + G[1][1] + G[2][2];
+  rate[0] = rJ * dv[0];
+  rate[1] = rJ * dv[1];
+  rate[2] = rJ * dv[2];
+  rate[3] = lamJ * div + T(2) * muJ * G[0][0];
+  rate[4] = lamJ * div + T(2) * muJ * G[1][1];
+  rate[5] = lamJ * div + T(2) * muJ * G[2][2];
+  rate[6] = muJ * (G[1][0] + G[0][1]);
+  rate[7] = muJ * (G[2][0] + G[0][2]);
+  rate[8] = muJ * (G[2][1] + G[1][2]);
+}
+
+// ---------------------------------------------------------------------------
 // the fused stage kernel
 //
 // Per plane a of the block's chunk:
@@ -257,9 +281,12 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
   const unsigned yh_col = yh_in ? (unsigned)yh_gy * px + (unsigned)yh_gx : 0u;
   // D+ reads v at R rows below and Q rows above a node, D- reads the flux at
   // Q below and R above: only those halo rows are loaded.  The last tile
-  // along r keeps every lower v row, which its boundary closure rows read.
-  const bool yh_v = yh_in && (yh_r >= H - R || y1 == nr);
-  const bool yh_f = yh_in && yh_r < H + R;
+  // along r (also when an edge row follows it) keeps every lower v row,
+  // which its boundary closure rows read.
+  const bool yh_v = yh_in && (yh_r >= H - R || y1 >= nr - 1);
+  // (with an edge row after the last tile, the boundary closure rows of that
+  // tile also read the flux of the edge row, which may lie beyond R)
+  const bool yh_f = yh_in && (yh_r < H + R || y1 == nr - 1);
   // x halo: columns x0-H..x0-1 and x0+64..x0+64+H-1, rows y0..y0+TY-1
   const int xh_c = tid / TY;
   const int xh_r = tid - xh_c * TY;
@@ -647,23 +674,8 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
         }
       }
 
-      // pointwise: stress rates (non-conservative metric form + Hooke)
-      T G[3][3];  // G[c][ii] = sum_xi M[xi][c] u[xi][ii]  (= J dv_ii/dx_c)
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int ii = 0; ii < 3; ++ii) G[c][ii] = mq[c] * u[0][ii] + mr[c] * u[1][ii] + ms[c] * u[2][ii];
-      const T div = G[0][0] + G[1][1] + G[2][2];
       T rate[9];
-      rate[0] = rJ * dv[0];
-      rate[1] = rJ * dv[1];
-      rate[2] = rJ * dv[2];
-      rate[3] = lamJ * div + T(2) * muJ * G[0][0];
-      rate[4] = lamJ * div + T(2) * muJ * G[1][1];
-      rate[5] = lamJ * div + T(2) * muJ * G[2][2];
-      rate[6] = muJ * (G[1][0] + G[0][1]);
-      rate[7] = muJ * (G[2][0] + G[0][2]);
-      rate[8] = muJ * (G[2][1] + G[1][2]);
+      node_rates(u, dv, mq, mr, ms, lamJ, muJ, rJ, rate);
 
       const T v[3] = {vq[0][R], vq[1][R], vq[2][R]};
 
@@ -755,6 +767,210 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
     }
   }
   flush_stores();
+}
+
+// ---------------------------------------------------------------------------
+// Edge nodes: when the tiles of the stage kernel cover [0, nq-1) x [0, nr-1)
+// exactly, the last q column (ex: nodes (nq-1, j, k)) and the last r row (ey:
+// nodes (i, nr-1, k), i < nq - ex) are computed here.  Each is a 2D strip
+// with a tangential axis (r for the column, q for the row) and the s axis;
+// its normal axis (q for the column, r for the row) is at the boundary.
+// A block owns 64 strip points x KZ planes: it stages v and the tangential
+// and s fluxes of the strip, with halos, in LDS, and takes the interior rows
+// of the tangential and s derivatives from there; boundary closure rows of
+// every axis (always the case along the normal axis) gather their columns
+// from memory.  Same arithmetic as the stage kernel: interior rows from the
+// interior stencil, boundary rows from the closure table, fluxes by flux3,
+// rates by node_rates, penalties by face_penalty, then the Runge-Kutta update.
+template <typename T, int ORDER, int KZ>
+__global__ __launch_bounds__(64 * KZ) void edge_kernel(const StageArgs<T> A, int ex, int ey) {
+  using S = Stencil<ORDER>;
+  constexpr int R = S::R, Q = S::Q, M = S::M;
+  constexpr int QD = R + Q + 1;
+  constexpr int NC = M + Q;  // columns of a closure row
+  static_assert(NC <= kMaxCols, "closure width");
+  constexpr int TABN = kMaxM * kMaxCols;
+  constexpr int H = Q;
+  constexpr int NT = 64 * KZ;
+  constexpr int PT = 64 + 2 * H, PK = KZ + 2 * H, NP = PT * PK;
+  __shared__ T ltab[kClosureTab * TABN];
+  __shared__ T lp[9 * NP];  // v (3), tangential flux (3), s flux (3)
+
+  const int nq = A.nq, nr = A.nr, ns = A.ns;
+  const int tid = threadIdx.y * 64 + threadIdx.x;
+  for (int e = tid; e < kClosureTab * TABN; e += NT) ltab[e] = A.tab[e];
+
+  // block -> strip, tangential tile, s tile
+  const int nkt = (ns + KZ - 1) / KZ;
+  const int ntc = ex ? (nr + 63) / 64 : 0;               // column strip tiles along r
+  const int nrow = nq - (ex ? 1 : 0);                     // row strip points along q
+  const int ntr = ey ? (nrow + 63) / 64 : 0;
+  int b = blockIdx.x;
+  if (b >= (ntc + ntr) * nkt) return;
+  const int st = b < ntc * nkt ? 0 : 1;                   // 0: column strip, 1: row strip
+  if (st == 1) b -= ntc * nkt;
+  const int tt = b % (st == 0 ? ntc : ntr), kt = b / (st == 0 ? ntc : ntr);
+  const int t0 = tt * 64, k0 = kt * KZ;
+  const int La = st == 0 ? nr : nq;                       // tangential axis length
+  const int Ln = st == 0 ? nr : nrow;                     // strip points computed
+  const int Nn = st == 0 ? nq : nr;                       // normal axis length
+  const int mt = st == 0 ? 3 : 0;                         // metric row of the tangential axis
+  const int mn = st == 0 ? 0 : 3;                         // metric row of the normal axis
+  const long long px = A.px, plane = (long long)A.plane, field = (long long)A.field;
+  const long long base = st == 0 ? (long long)(nq - 1) : (long long)(nr - 1) * px;
+  const long long tstr = st == 0 ? px : 1, nstr = st == 0 ? 1 : px;
+  const T iht = st == 0 ? A.inv_h[1] : A.inv_h[0];
+  const T ihn = st == 0 ? A.inv_h[0] : A.inv_h[1];
+  const T ihs = A.inv_h[2];
+  const T* __restrict__ qin = A.qin;
+  const T* __restrict__ cf = A.coef;
+
+  // stage the patch
+  for (int e = tid; e < NP; e += NT) {
+    const int pk = e / PT, pt = e - pk * PT;
+    const int t = t0 - H + pt, k = k0 - H + pk;
+    if (t < 0 || t >= La || k < 0 || k >= ns) continue;
+    const long long o = (long long)k * plane + base + (long long)t * tstr;
+    T sg[6], f[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) lp[c * NP + e] = qin[c * field + o];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sg[c] = qin[(3 + c) * field + o];
+    flux3(cf[mt * field + o], cf[(mt + 1) * field + o], cf[(mt + 2) * field + o], sg[0], sg[1], sg[2], sg[3], sg[4],
+          sg[5], f);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) lp[(3 + c) * NP + e] = f[c];
+    flux3(cf[6 * field + o], cf[7 * field + o], cf[8 * field + o], sg[0], sg[1], sg[2], sg[3], sg[4], sg[5], f);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) lp[(6 + c) * NP + e] = f[c];
+  }
+  __syncthreads();
+
+  const int t = t0 + threadIdx.x, k = k0 + threadIdx.y;
+  if (t >= Ln || k >= ns) return;
+  const long long o = (long long)k * plane + base + (long long)t * tstr;
+  const int pme = (threadIdx.y + H) * PT + threadIdx.x + H;  // own patch point
+
+  // derivatives along one axis at position p of n: D+ of v into uo, D- of
+  // the flux added to dv; gv(d, c) / gf(d, f) return v and the flux at the
+  // point d positions away along the axis (interior rows), cv / cflux the
+  // same from memory (closure rows)
+  T dv[3] = {T(0), T(0), T(0)};
+  auto derivs = [&](int p, int n, T ih, auto gv, auto gf, auto cvf, auto cflux, T uo[3]) {
+    T sp[3] = {T(0), T(0), T(0)}, sm[3] = {T(0), T(0), T(0)};
+    if (p >= M && p < n - M) {
+#pragma unroll
+      for (int s = 0; s < QD; ++s) {
+        T f[3];
+        gf(R - s, f);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          sp[c] += T(S::a[s]) * gv(s - R, c);
+          sm[c] += T(S::a[s]) * f[c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        uo[c] = sp[c] * ih;
+        dv[c] -= sm[c] * ih;
+      }
+    } else {
+      const bool left = p < M;
+      const int row = left ? p : n - 1 - p;
+      const int tb = left ? 0 : 2 * TABN;
+#pragma unroll
+      for (int cc = 0; cc < NC; ++cc) {
+        const int d = (left ? cc : n - 1 - cc) - p;
+        const T cp = ltab[tb + row * kMaxCols + cc];
+        const T cm = ltab[tb + TABN + row * kMaxCols + cc];
+        T f[3];
+        cflux(d, f);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          sp[c] += cp * cvf(d, c);
+          sm[c] += cm * f[c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        uo[c] = sp[c] * ih;
+        dv[c] += sm[c] * ih;
+      }
+    }
+  };
+  // v and the flux of metric row m at the point d steps of stride str away
+  auto mem_v = [&](long long str) { return [=](int d, int c) { return qin[c * field + o + d * str]; }; };
+  auto mem_f = [&](long long str, int m) {
+    return [=](int d, T f[3]) {
+      const long long od = o + d * str;
+      flux3(cf[m * field + od], cf[(m + 1) * field + od], cf[(m + 2) * field + od], qin[3 * field + od],
+            qin[4 * field + od], qin[5 * field + od], qin[6 * field + od], qin[7 * field + od], qin[8 * field + od],
+            f);
+    };
+  };
+  T un[3], ut[3], us[3];
+  // normal axis: closure rows of the far boundary
+  derivs(Nn - 1, Nn, ihn, mem_v(nstr), mem_f(nstr, mn), mem_v(nstr), mem_f(nstr, mn), un);
+  // tangential axis and s axis: interior rows from the patch
+  derivs(t, La, iht, [&](int d, int c) { return lp[c * NP + pme + d]; },
+         [&](int d, T f[3]) {
+#pragma unroll
+           for (int c = 0; c < 3; ++c) f[c] = lp[(3 + c) * NP + pme + d];
+         },
+         mem_v(tstr), mem_f(tstr, mt), ut);
+  derivs(k, ns, ihs, [&](int d, int c) { return lp[c * NP + pme + d * PT]; },
+         [&](int d, T f[3]) {
+#pragma unroll
+           for (int c = 0; c < 3; ++c) f[c] = lp[(6 + c) * NP + pme + d * PT];
+         },
+         mem_v(plane), mem_f(plane, 6), us);
+
+  T u[3][3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    u[0][c] = st == 0 ? un[c] : ut[c];  // q
+    u[1][c] = st == 0 ? ut[c] : un[c];  // r
+    u[2][c] = us[c];                    // s
+  }
+  const int i = st == 0 ? nq - 1 : t, j = st == 0 ? t : nr - 1;
+  T mq[3], mr[3], ms[3], v[3], sg[6];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    mq[c] = cf[c * field + o];
+    mr[c] = cf[(3 + c) * field + o];
+    ms[c] = cf[(6 + c) * field + o];
+    v[c] = lp[c * NP + pme];
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) sg[c] = qin[(3 + c) * field + o];
+  T rate[9];
+  node_rates(u, dv, mq, mr, ms, cf[9 * field + o], cf[10 * field + o], cf[11 * field + o], rate);
+
+  if (i == 0 || i == nq - 1 || j == 0 || j == nr - 1 || k == 0 || k == ns - 1) {
+    T fc[kNumFaceCoef];
+    auto face = [&](int f, std::size_t idx, T eps) {
+#pragma unroll
+      for (int kk = 0; kk < kNumFaceCoef; ++kk) fc[kk] = A.face[A.face_off[f] + idx + (std::size_t)kk * A.face_n[f]];
+      face_penalty(fc, A.gamma[f], eps, A.traction[f], v, sg, rate);
+    };
+    if (i == 0) face(0, (std::size_t)k * nr + j, T(-1));
+    if (i == nq - 1) face(1, (std::size_t)k * nr + j, T(1));
+    if (j == 0) face(2, (std::size_t)k * nq + i, T(-1));
+    if (j == nr - 1) face(3, (std::size_t)k * nq + i, T(1));
+    if (k == 0) face(4, (std::size_t)j * nq + i, T(-1));
+    if (k == ns - 1) face(5, (std::size_t)j * nq + i, T(1));
+  }
+
+  const T dt = A.dt, Ak = A.Ak, Bk = A.Bk;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    const long long oc = (long long)c * field + o;
+    const T dqo = A.read_dq ? A.dq[oc] : T(0);
+    const T d = dt * rate[c] + Ak * dqo;
+    const T q0 = (c < 3) ? v[c] : sg[c - 3];
+    A.dq[oc] = d;
+    A.qout[oc] = q0 + Bk * d;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -860,6 +1076,23 @@ hipError_t launch_stage(int order, int ty, const StageArgs<T>& a, hipStream_t st
 }
 
 template <typename T>
+hipError_t launch_edge(int order, const StageArgs<T>& a, int ex, int ey, hipStream_t st) {
+  constexpr int KZ = 8;
+  const int nkt = (a.ns + KZ - 1) / KZ;
+  const int nb = ((ex ? (a.nr + 63) / 64 : 0) + (ey ? (a.nq - (ex ? 1 : 0) + 63) / 64 : 0)) * nkt;
+  if (nb == 0) return hipSuccess;
+  if (order == 2)
+    hipLaunchKernelGGL((edge_kernel<T, 2, KZ>), dim3(nb), dim3(64, KZ), 0, st, a, ex, ey);
+  else if (order == 4)
+    hipLaunchKernelGGL((edge_kernel<T, 4, KZ>), dim3(nb), dim3(64, KZ), 0, st, a, ex, ey);
+  else if (order == 6)
+    hipLaunchKernelGGL((edge_kernel<T, 6, KZ>), dim3(nb), dim3(64, KZ), 0, st, a, ex, ey);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_source(const SourceArgs<T>& s, int nsrc, hipStream_t st) {
   hipLaunchKernelGGL(source_kernel<T>, dim3(nsrc), dim3(256), 0, st, s);
   return hipGetLastError();
@@ -880,6 +1113,8 @@ hipError_t launch_energy(const EnergyArgs<T>& e, int nblocks, hipStream_t st) {
 
 template hipError_t launch_stage<float>(int, int, const StageArgs<float>&, hipStream_t);
 template hipError_t launch_stage<double>(int, int, const StageArgs<double>&, hipStream_t);
+template hipError_t launch_edge<float>(int, const StageArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_edge<double>(int, const StageArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_source<float>(const SourceArgs<float>&, int, hipStream_t);
 template hipError_t launch_source<double>(const SourceArgs<double>&, int, hipStream_t);
 template hipError_t launch_record<float>(const float*, std::size_t, const long long*, int, float*, hipStream_t);

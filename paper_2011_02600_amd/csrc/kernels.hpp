@@ -62,6 +62,8 @@ struct EnergyArgs {
 template <typename T>
 hipError_t launch_stage(int order, int ty, const StageArgs<T>& a, hipStream_t st);
 template <typename T>
+hipError_t launch_edge(int order, const StageArgs<T>& a, int ex, int ey, hipStream_t st);
+template <typename T>
 hipError_t launch_source(const SourceArgs<T>& s, int nsrc, hipStream_t st);
 template <typename T>
 hipError_t launch_record(const T* q, std::size_t field, const long long* off, int nrec, T* out,

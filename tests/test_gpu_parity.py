@@ -89,7 +89,13 @@ RHS_CASES = [
     (6, (17, 13, 131), "f64", 0),
     (6, (17, 13, 131), "f32", 0),
     (6, (25, 21, 17), "f64", 1),
-    (6, (13, 30, 65), "f32", 1),
+    (6, (13, 30, 65), "f32", 1),      # last q column by the edge kernel
+    # sizes whose last q column and / or last r row go to the edge kernel
+    # (n - 1 a multiple of the 128-byte line along q, of the tile height along r)
+    (4, (13, 17, 65), "f64", 0),
+    (6, (15, 25, 97), "f64", 1),
+    (2, (9, 17, 40), "f32", 0),
+    (6, (14, 33, 129), "f32", 0),
 ]
 
 
@@ -125,12 +131,16 @@ def test_rhs_parity(order, shape, dtype, variant):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_topo_layer_small_100_steps(dtype):
+@pytest.mark.parametrize("size", [(49, 45, 37), (65, 41, 33)])
+def test_topo_layer_small_100_steps(dtype, size):
     """The curvilinear layered workload (topography, transfinite mesh, soft
     layer over a half-space, Ricker moment source, surface receivers) at a
-    reduced size: 100 steps, state and receiver traces against the oracle."""
-    say("case: topo_layer 49x45x37 order 6 %s 100 steps" % dtype)
-    wl = W.topo_layer(nq=49, nr=45, ns=37, nrec_side=4)
+    reduced size: 100 steps, state and receiver traces against the oracle.
+    The second size has its last q column and r row on the edge kernel, like
+    the full-size workload."""
+    nq, nr, ns = size
+    say("case: topo_layer %dx%dx%d order 6 %s 100 steps" % (nq, nr, ns, dtype))
+    wl = W.topo_layer(nq=nq, nr=nr, ns=ns, nrec_side=4)
     s = make_solver(wl["xyz"], 6, dtype, wl["gamma"], medium=(wl["rho"], wl["cp"], wl["cs"]))
     s.add_source(wl["src_xi"], wl["src_M"], 0, wl["src_f0"], wl["src_t0"])
     traces = s.record(wl["receivers"], 100)
@@ -205,16 +215,19 @@ def test_full_size_energy_decreases():
     assert abs(eo - es[-1]) <= 1e-5 * eo
 
 
-def test_launch_shapes_give_identical_results():
+@pytest.mark.parametrize("size", [(70, 37, 29), (65, 33, 29)])
+def test_launch_shapes_give_identical_results(size):
     """For a given tile height every node is computed by the same
     instructions whatever the s-chunking: results are bitwise identical across
     z-chunk sizes.  Different tile heights are different kernel instantiations
     (the compiler may contract or order operations differently), so across
-    them the results agree to rounding."""
-    say("case: launch-shape invariance order 4 f32 70x37x29")
-    xyz = W.warped_mesh(70, 37, 29, seed=3)
-    med = W.random_medium((29, 37, 70), 4)
-    Q = W.random_state((29, 37, 70), 6, smooth=True)
+    them the results agree to rounding.  The second size uses the edge
+    kernel for its last q column and r row."""
+    nq, nr, ns = size
+    say("case: launch-shape invariance order 4 f32 %dx%dx%d" % size)
+    xyz = W.warped_mesh(nq, nr, ns, seed=3)
+    med = W.random_medium((ns, nr, nq), 4)
+    Q = W.random_state((ns, nr, nq), 6, smooth=True)
     outs = {}
     for ty, zc in ((8, 0), (8, 5), (8, 1), (16, 29), (16, 3)):
         s = make_solver(xyz, 4, "f32", [0, 1, 0, 0, -1, 1], medium=med)
