@@ -84,6 +84,7 @@ struct sbp_ctx {
   std::size_t face_n[6] = {};
   int px = 0;
   std::size_t plane = 0, field = 0;
+  NodeMap nm{};   // node -> element offset in a field
   // host copies kept for the material and source set-up
   std::vector<double> J;           // Jacobian (dense)
   std::vector<double> Mface[6];    // M[xi][0..2] on face f (3 * face_n)
@@ -120,11 +121,18 @@ int check_dims(int nq, int nr, int ns, int order, int dtype) {
 void layout(sbp_ctx* h) {
   const int es = h->esize;
   const Geometry& g = h->g;
-  // rows start on 128-byte lines (the memory request size)
+  // The first nq - 1 columns in rows starting on 128-byte lines (the memory
+  // request size); column nq - 1 in a compact array after them (NodeMap).
   const int line = 128 / es;
-  h->px = (g.nq + line - 1) / line * line;
+  h->px = (g.nq - 1 + line - 1) / line * line;
   h->plane = (std::size_t)h->px * g.nr;
-  h->field = h->plane * g.ns;
+  const std::size_t ncol = (std::size_t)g.nr * g.ns;
+  h->field = h->plane * g.ns + (ncol + line - 1) / line * line;
+  h->nm.plane = (long long)h->plane;
+  h->nm.cbase = (long long)(h->plane * g.ns);
+  h->nm.px = h->px;
+  h->nm.nr = g.nr;
+  h->nm.nqm = g.nq - 1;
   std::size_t o = 0;
   auto take = [&](std::size_t bytes) {
     std::size_t at = o;
@@ -147,6 +155,35 @@ void layout(sbp_ctx* h) {
   h->off_bounds = take((std::size_t)(g.nq + g.nr + g.ns + 16) * sizeof(int));
   h->off_tab = take((std::size_t)kClosureTab * kMaxM * kMaxCols * es);
   h->total = o;
+}
+
+// Copies of nf fields between a dense (ns, nr, nq) array and device fields in
+// the NodeMap layout: the first nq - 1 columns as pitched rows, column nq - 1
+// into the compact array.
+int copy_in(sbp_ctx* h, char* dst, const void* src, int nf, hipMemcpyKind kind) {
+  const Geometry& g = h->g;
+  const std::size_t es = h->esize, rows = (std::size_t)g.nr * g.ns;
+  for (int f = 0; f < nf; ++f) {
+    char* d = dst + (std::size_t)f * h->field * es;
+    const char* s = (const char*)src + (std::size_t)f * g.n * es;
+    HIPCHK(hipMemcpy2DAsync(d, h->px * es, s, g.nq * es, (g.nq - 1) * es, rows, kind, h->stream));
+    HIPCHK(hipMemcpy2DAsync(d + (std::size_t)h->nm.cbase * es, es, s + (g.nq - 1) * es, g.nq * es, es, rows, kind,
+                            h->stream));
+  }
+  return SBP_OK;
+}
+
+int copy_out(sbp_ctx* h, void* dst, const char* src, int nf, hipMemcpyKind kind) {
+  const Geometry& g = h->g;
+  const std::size_t es = h->esize, rows = (std::size_t)g.nr * g.ns;
+  for (int f = 0; f < nf; ++f) {
+    char* d = (char*)dst + (std::size_t)f * g.n * es;
+    const char* s = src + (std::size_t)f * h->field * es;
+    HIPCHK(hipMemcpy2DAsync(d, g.nq * es, s, h->px * es, (g.nq - 1) * es, rows, kind, h->stream));
+    HIPCHK(hipMemcpy2DAsync(d + (g.nq - 1) * es, g.nq * es, s + (std::size_t)h->nm.cbase * es, es, es, rows, kind,
+                            h->stream));
+  }
+  return SBP_OK;
 }
 
 // ---- one-dimensional SBP operators on the host (double) ----------------------
@@ -197,8 +234,8 @@ int upload_field(sbp_ctx* h, std::size_t off, const double* src) {
   const Geometry& g = h->g;
   std::vector<T> tmp(g.n);
   for (std::size_t n = 0; n < g.n; ++n) tmp[n] = (T)src[n];
-  HIPCHK(hipMemcpy2DAsync(h->ws + off, h->px * sizeof(T), tmp.data(), g.nq * sizeof(T), g.nq * sizeof(T),
-                          (std::size_t)g.nr * g.ns, hipMemcpyHostToDevice, h->stream));
+  int rc = copy_in(h, h->ws + off, tmp.data(), 1, hipMemcpyHostToDevice);
+  if (rc) return rc;
   HIPCHK(hipStreamSynchronize(h->stream));
   return SBP_OK;
 }
@@ -332,11 +369,11 @@ int prepare_bounds(sbp_ctx* h) {
   if (!h->bounds_dirty) return SBP_OK;
   const Geometry& g = h->g;
   const int line = 128 / h->esize;  // points per 128-byte line
-  // Grids of 64k + 1 points along q (more generally line * k + 1) and
-  // ty * k + 1 along r: the tiles cover [0, nq - 1) x [0, nr - 1) exactly and
-  // the edge kernel takes the last column and row, so that no tile is
-  // narrower than a line or shorter than ty.
-  h->ex = ((g.nq - 1) % line == 0 && g.nq - 1 >= 64) ? 1 : 0;
+  // The tiles cover the first nq - 1 columns (the layout keeps column nq - 1
+  // apart, NodeMap); the edge kernel computes column nq - 1 and, when nr - 1
+  // is a multiple of the tile height, also row nr - 1 so that no tile along
+  // r is shorter than ty (for nq = 64 k + 1, nr = ty k + 1 every tile is full).
+  h->ex = 1;
   h->ey = ((g.nr - 1) % h->ty == 0 && g.nr - 1 >= 2 * h->ty) ? 1 : 0;
   std::vector<int> xb = tile_bounds_aligned(g.nq - h->ex, line, h->cl.m);
   std::vector<int> yb = tile_bounds(g.nr - h->ey, h->ty, h->cl.m);
@@ -403,6 +440,7 @@ StageArgs<T> stage_args(sbp_ctx* h) {
     a.traction[f] = (h->sat_variant == SBP_SAT_TRACTION && h->gamma[f] == 1.0) ? 1 : 0;
   }
   a.bounds = (const int*)(h->ws + h->off_bounds);
+  a.nm = h->nm;
   a.plane = h->plane;
   a.field = h->field;
   a.px = h->px;
@@ -438,6 +476,7 @@ int run_stage(sbp_ctx* h, StageArgs<T>& a, int k, double dt, double tstage, bool
     s.dq = dq;
     s.qout = rhs_only ? nullptr : qout;
     s.wm = (const T*)(h->ws + h->off_src);
+    s.nm = h->nm;
     s.plane = h->plane;
     s.field = h->field;
     s.px = h->px;
@@ -494,10 +533,7 @@ int do_rhs(sbp_ctx* h, void* out, double t) {
   T* qout = h->cur ? qa : qb;
   rc = run_stage<T>(h, a, 0, 1.0, t, true, qin, qout);
   if (rc) return rc;
-  const Geometry& g = h->g;
-  HIPCHK(hipMemcpy2DAsync(out, g.nq * sizeof(T), h->ws + h->off_dq, h->px * sizeof(T), g.nq * sizeof(T),
-                          (std::size_t)9 * g.nr * g.ns, hipMemcpyDeviceToDevice, h->stream));
-  return SBP_OK;
+  return copy_out(h, out, h->ws + h->off_dq, 9, hipMemcpyDeviceToDevice);
 }
 
 template <typename T>
@@ -507,6 +543,7 @@ int do_energy(sbp_ctx* h, double* E) {
   e.q = (const T*)(h->ws + (h->cur ? h->off_qb : h->off_qa));
   e.coef = (const T*)(h->ws + h->off_coef);
   e.part = (double*)(h->ws + h->off_part);
+  e.nm = h->nm;
   e.plane = h->plane;
   e.field = h->field;
   e.px = h->px;
@@ -740,11 +777,9 @@ int sbp_clear_sources(sbp_handle h) {
 
 int sbp_set_state(sbp_handle h, const void* q, int q_is_device, double t) {
   if (!h || !q) return fail(SBP_EINVAL, "NULL argument");
-  const Geometry& g = h->g;
-  const std::size_t es = h->esize;
   char* dst = h->ws + (h->cur ? h->off_qb : h->off_qa);
-  HIPCHK(hipMemcpy2DAsync(dst, h->px * es, q, g.nq * es, g.nq * es, (std::size_t)9 * g.nr * g.ns,
-                          q_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, h->stream));
+  int rc = copy_in(h, dst, q, 9, q_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
+  if (rc) return rc;
   if (!q_is_device) HIPCHK(hipStreamSynchronize(h->stream));
   h->t = t;
   return SBP_OK;
@@ -752,11 +787,9 @@ int sbp_set_state(sbp_handle h, const void* q, int q_is_device, double t) {
 
 int sbp_get_state(sbp_handle h, void* q, int q_is_device, double* t_out) {
   if (!h || !q) return fail(SBP_EINVAL, "NULL argument");
-  const Geometry& g = h->g;
-  const std::size_t es = h->esize;
   const char* src = h->ws + (h->cur ? h->off_qb : h->off_qa);
-  HIPCHK(hipMemcpy2DAsync(q, g.nq * es, src, h->px * es, g.nq * es, (std::size_t)9 * g.nr * g.ns,
-                          q_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, h->stream));
+  int rc = copy_out(h, q, src, 9, q_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
+  if (rc) return rc;
   if (!q_is_device) HIPCHK(hipStreamSynchronize(h->stream));
   if (t_out) *t_out = h->t;
   return SBP_OK;
@@ -776,7 +809,7 @@ int sbp_record(sbp_handle h, int nrec, const int* ijk, void* out_device, int max
     const int i = ijk[3 * r], j = ijk[3 * r + 1], k = ijk[3 * r + 2];
     if (i < 0 || i >= g.nq || j < 0 || j >= g.nr || k < 0 || k >= g.ns)
       return fail(SBP_EINVAL, "receiver %d outside the grid", r);
-    off[r] = (long long)k * h->plane + (long long)j * h->px + i;
+    off[r] = h->nm(i, j, k);
   }
   HIPCHK(hipMemcpyAsync(h->ws + h->off_rec, off.data(), nrec * sizeof(long long), hipMemcpyHostToDevice,
                         h->stream));

@@ -38,21 +38,21 @@ bool build_closure(int order, Closure* out, const char** err);
 // kappa = |M_xi| / (J h_xi w_0).
 enum FaceCoef { FN_X = 0, FN_Y, FN_Z, F_ZP, F_ZS, F_IZP, F_IZS, F_KR, F_KL, F_KM };
 
-// Element layout of the device arrays of one handle (all counts in elements
-// of the handle's dtype, relative to the start of the workspace).
-struct Layout {
-  int nq = 0, nr = 0, ns = 0;
-  int px = 0;             // x pitch (elements), multiple of 16
-  std::size_t plane = 0;  // px * nr
-  std::size_t field = 0;  // plane * ns
-  std::size_t q_a = 0, q_b = 0, dq = 0, coef = 0;  // 9, 9, 9, 12 fields
-  std::size_t face[6] = {};   // kNumFaceCoef arrays of face size each
-  std::size_t face_n[6] = {}; // nodes per face
-  std::size_t face_na[6] = {};// fast extent of the face array
-  std::size_t src = 0;        // kMaxSources * (kMaxSrcWidth^3 * 6) weights
-  std::size_t part = 0;       // energy partial sums (double, bytes offset)
-  std::size_t bounds = 0;     // int tile bounds (bytes offset)
-  std::size_t total_bytes = 0;
+// Position of node (i, j, k) in a field (element offset).  The first nq - 1
+// columns of every (j, k) row lie in rows of pitch px (a multiple of the
+// 128-byte line, so that rows and 64-point tiles start on lines); column
+// nq - 1 of all rows is stored after them, compactly in (k, j) order, where
+// its values fill whole lines instead of one value per line.
+struct NodeMap {
+  long long plane = 0;  // px * nr
+  long long cbase = 0;  // offset of the last-column array: plane * ns
+  int px = 0, nr = 0, nqm = 0;  // nqm = nq - 1
+#if defined(__HIPCC__)
+  __host__ __device__
+#endif
+  long long operator()(int i, int j, int k) const {
+    return i < nqm ? (long long)k * plane + (long long)j * px + i : cbase + (long long)k * nr + j;
+  }
 };
 
 }  // namespace sbp

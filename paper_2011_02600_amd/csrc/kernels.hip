@@ -264,7 +264,7 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
   const int i = x0 + tx, j = y0 + ty;
   const int nq = A.nq, nr = A.nr, ns = A.ns;
   const bool act = (i < x1) && (j < y1);    // node computed by this block
-  const bool ing = (i < nq) && (j < nr);    // node staged in LDS (own or halo of the tile)
+  const bool ing = (i < x1) && (j < nr);    // node staged in LDS (own or halo of the tile)
   const unsigned px = A.px, plane = A.plane;
   const std::size_t field = A.field;
   const unsigned col = (unsigned)j * px + (unsigned)i;
@@ -272,11 +272,11 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
   const Arr<T, BUF> gq(A.qin, field), gc(A.coef, field), gd(A.dq, field), go(A.qout, field);
   for (int e = threadIdx.y * 64 + threadIdx.x; e < kClosureTab * TABN; e += NT) ltab[e] = A.tab[e];
 
-  // y halo: rows y0-H..y0-1 and y0+TY..y0+TY+H-1, columns x0..x0+63
+  // y halo: rows y0-H..y0-1 and y0+TY..y0+TY+H-1, columns x0..x1-1
   const int yh_r = tid >> 6;
   const int yh_gy = (yh_r < H) ? (y0 - H + yh_r) : (y0 + TY + yh_r - H);
   const int yh_gx = x0 + (tid & 63);
-  const bool yh_in = tid < NYH && yh_gx < nq && yh_gy >= 0 && yh_gy < nr;
+  const bool yh_in = tid < NYH && yh_gx < x1 && yh_gy >= 0 && yh_gy < nr;
   const int yh_ly = (yh_r < H) ? yh_r : TY + yh_r;   // row in the v / F_r windows
   const unsigned yh_col = yh_in ? (unsigned)yh_gy * px + (unsigned)yh_gx : 0u;
   // D+ reads v at R rows below and Q rows above a node, D- reads the flux at
@@ -287,14 +287,17 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
   // (with an edge row after the last tile, the boundary closure rows of that
   // tile also read the flux of the edge row, which may lie beyond R)
   const bool yh_f = yh_in && (yh_r < H + R || y1 == nr - 1);
-  // x halo: columns x0-H..x0-1 and x0+64..x0+64+H-1, rows y0..y0+TY-1
+  // x halo: columns x0-H..x0-1 and x1..x1+H-1, rows y0..y0+TY-1.  Column
+  // nq-1 (the right halo of the last tile) is read from the last-column
+  // array of the fields.
   const int xh_c = tid / TY;
   const int xh_r = tid - xh_c * TY;
-  const int xh_gx = (xh_c < H) ? (x0 - H + xh_c) : (x0 + 64 + xh_c - H);
+  const int xh_gx = (xh_c < H) ? (x0 - H + xh_c) : (x1 + xh_c - H);
   const int xh_gy = y0 + xh_r;
   const bool xh_in = tid < NXH && xh_gx >= 0 && xh_gx < nq && xh_gy < nr;
-  const int xh_lx = (xh_c < H) ? xh_c : 64 + xh_c;  // column in the v / F_q windows
-  const unsigned xh_col = xh_in ? (unsigned)xh_gy * px + (unsigned)xh_gx : 0u;
+  const int xh_lx = (xh_c < H) ? xh_c : (x1 - x0) + xh_c;  // column in the v / F_q windows
+  const bool xh_edge = xh_in && xh_gx == A.nm.nqm;
+  const unsigned xh_col = (xh_in && !xh_edge) ? (unsigned)xh_gy * px + (unsigned)xh_gx : 0u;
   // waves holding x-halo lanes (a wave-uniform condition)
   const bool xh_wave = __builtin_amdgcn_readfirstlane(ty) * 64 < NXH;
 
@@ -431,7 +434,7 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
 #pragma unroll
     for (int c = 0; c < 3; ++c) p_hy[9 + c] = gc.ld(3 + c, ohf);
     if (xh_wave) {
-      const unsigned ox = pa + xh_col;
+      const unsigned ox = xh_edge ? (unsigned)(A.nm.cbase + (long long)a * nr + xh_gy) : pa + xh_col;
 #pragma unroll
       for (int c = 0; c < 9; ++c) p_hx[c] = gq.ld(c, ox);
 #pragma unroll
@@ -795,6 +798,9 @@ __global__ __launch_bounds__(64 * KZ) void edge_kernel(const StageArgs<T> A, int
   constexpr int PT = 64 + 2 * H, PK = KZ + 2 * H, NP = PT * PK;
   __shared__ T ltab[kClosureTab * TABN];
   __shared__ T lp[9 * NP];  // v (3), tangential flux (3), s flux (3)
+  // column strip: sums over columns nq-2 .. nq-NC of its q closure row
+  // (D+ part 3, D- part 3) per node of the block
+  __shared__ T lqc[6 * NT];
 
   const int nq = A.nq, nr = A.nr, ns = A.ns;
   const int tid = threadIdx.y * 64 + threadIdx.x;
@@ -816,9 +822,12 @@ __global__ __launch_bounds__(64 * KZ) void edge_kernel(const StageArgs<T> A, int
   const int Nn = st == 0 ? nq : nr;                       // normal axis length
   const int mt = st == 0 ? 3 : 0;                         // metric row of the tangential axis
   const int mn = st == 0 ? 0 : 3;                         // metric row of the normal axis
-  const long long px = A.px, plane = (long long)A.plane, field = (long long)A.field;
-  const long long base = st == 0 ? (long long)(nq - 1) : (long long)(nr - 1) * px;
-  const long long tstr = st == 0 ? px : 1, nstr = st == 0 ? 1 : px;
+  const long long field = (long long)A.field;
+  const NodeMap nm = A.nm;
+  // element offset of the point (tangential t, s k) displaced dn along the normal axis
+  auto at = [&](int dn, int t, int k) -> long long {
+    return st == 0 ? nm(nq - 1 + dn, t, k) : nm(t, nr - 1 + dn, k);
+  };
   const T iht = st == 0 ? A.inv_h[1] : A.inv_h[0];
   const T ihn = st == 0 ? A.inv_h[0] : A.inv_h[1];
   const T ihs = A.inv_h[2];
@@ -830,7 +839,7 @@ __global__ __launch_bounds__(64 * KZ) void edge_kernel(const StageArgs<T> A, int
     const int pk = e / PT, pt = e - pk * PT;
     const int t = t0 - H + pt, k = k0 - H + pk;
     if (t < 0 || t >= La || k < 0 || k >= ns) continue;
-    const long long o = (long long)k * plane + base + (long long)t * tstr;
+    const long long o = at(0, t, k);
     T sg[6], f[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) lp[c * NP + e] = qin[c * field + o];
@@ -844,11 +853,52 @@ __global__ __launch_bounds__(64 * KZ) void edge_kernel(const StageArgs<T> A, int
 #pragma unroll
     for (int c = 0; c < 3; ++c) lp[(6 + c) * NP + e] = f[c];
   }
+  if (st == 0) {
+    // The q closure row of a column node reads columns nq-NC .. nq-1 of the
+    // node's row.  Sixteen lanes per node (lane l: column nq-16+l) load them
+    // together, so that a load touches a few lines instead of one per lane,
+    // and sum in a fixed butterfly; column nq-1 is added by the node itself.
+    const int grp = tid >> 4, l = tid & 15;
+    const int col = nq - 16 + l, cc = 15 - l;  // cc: column index of the closure row
+    const T cp = (cc >= 1 && cc < NC) ? ltab[2 * TABN + cc] : T(0);
+    const T cm = (cc >= 1 && cc < NC) ? ltab[3 * TABN + cc] : T(0);
+#pragma unroll 2
+    for (int nd = grp; nd < NT; nd += NT / 16) {
+      const int tq = t0 + (nd & 63), kq = k0 + nd / 64;
+      T pv[3] = {T(0), T(0), T(0)}, pf[3] = {T(0), T(0), T(0)};
+      if (tq < Ln && kq < ns && cc >= 1 && cc < NC && col >= 0) {
+        const long long op = nm(col, tq, kq);
+        T f[3];
+        flux3(cf[op], cf[field + op], cf[2 * field + op], qin[3 * field + op], qin[4 * field + op],
+              qin[5 * field + op], qin[6 * field + op], qin[7 * field + op], qin[8 * field + op], f);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          pv[c] = cp * qin[c * field + op];
+          pf[c] = cm * f[c];
+        }
+      }
+#pragma unroll
+      for (int w = 8; w >= 1; w >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          pv[c] += __shfl_xor(pv[c], w, 16);
+          pf[c] += __shfl_xor(pf[c], w, 16);
+        }
+      }
+      if (l == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          lqc[c * NT + nd] = pv[c];
+          lqc[(3 + c) * NT + nd] = pf[c];
+        }
+      }
+    }
+  }
   __syncthreads();
 
   const int t = t0 + threadIdx.x, k = k0 + threadIdx.y;
   if (t >= Ln || k >= ns) return;
-  const long long o = (long long)k * plane + base + (long long)t * tstr;
+  const long long o = at(0, t, k);
   const int pme = (threadIdx.y + H) * PT + threadIdx.x + H;  // own patch point
 
   // derivatives along one axis at position p of n: D+ of v into uo, D- of
@@ -898,32 +948,45 @@ __global__ __launch_bounds__(64 * KZ) void edge_kernel(const StageArgs<T> A, int
       }
     }
   };
-  // v and the flux of metric row m at the point d steps of stride str away
-  auto mem_v = [&](long long str) { return [=](int d, int c) { return qin[c * field + o + d * str]; }; };
-  auto mem_f = [&](long long str, int m) {
+  // v and the flux of metric row m at the point d steps away along axis ax
+  // (0 normal, 1 tangential, 2 s), read from memory
+  auto pt_off = [=](int ax, int d) { return at(ax == 0 ? d : 0, ax == 1 ? t + d : t, ax == 2 ? k + d : k); };
+  auto mem_v = [&](int ax) { return [=](int d, int c) { return qin[c * field + pt_off(ax, d)]; }; };
+  auto mem_f = [&](int ax, int m) {
     return [=](int d, T f[3]) {
-      const long long od = o + d * str;
+      const long long od = pt_off(ax, d);
       flux3(cf[m * field + od], cf[(m + 1) * field + od], cf[(m + 2) * field + od], qin[3 * field + od],
             qin[4 * field + od], qin[5 * field + od], qin[6 * field + od], qin[7 * field + od], qin[8 * field + od],
             f);
     };
   };
   T un[3], ut[3], us[3];
-  // normal axis: closure rows of the far boundary
-  derivs(Nn - 1, Nn, ihn, mem_v(nstr), mem_f(nstr, mn), mem_v(nstr), mem_f(nstr, mn), un);
+  // normal axis: closure row of the far boundary
+  if (st == 0) {
+    T f[3];
+    mem_f(0, mn)(0, f);
+    const T cp = ltab[2 * TABN], cm = ltab[3 * TABN];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      un[c] = (lqc[c * NT + tid] + cp * lp[c * NP + pme]) * ihn;
+      dv[c] += (lqc[(3 + c) * NT + tid] + cm * f[c]) * ihn;
+    }
+  } else {
+    derivs(Nn - 1, Nn, ihn, mem_v(0), mem_f(0, mn), mem_v(0), mem_f(0, mn), un);
+  }
   // tangential axis and s axis: interior rows from the patch
   derivs(t, La, iht, [&](int d, int c) { return lp[c * NP + pme + d]; },
          [&](int d, T f[3]) {
 #pragma unroll
            for (int c = 0; c < 3; ++c) f[c] = lp[(3 + c) * NP + pme + d];
          },
-         mem_v(tstr), mem_f(tstr, mt), ut);
+         mem_v(1), mem_f(1, mt), ut);
   derivs(k, ns, ihs, [&](int d, int c) { return lp[c * NP + pme + d * PT]; },
          [&](int d, T f[3]) {
 #pragma unroll
            for (int c = 0; c < 3; ++c) f[c] = lp[(6 + c) * NP + pme + d * PT];
          },
-         mem_v(plane), mem_f(plane, 6), us);
+         mem_v(2), mem_f(2, 6), us);
 
   T u[3][3];
 #pragma unroll
@@ -982,8 +1045,7 @@ __global__ void source_kernel(SourceArgs<T> S) {
   const int n = w * w * w;
   for (int t = threadIdx.x; t < n; t += blockDim.x) {
     const int a = t % w, b = (t / w) % w, c = t / (w * w);
-    const std::size_t o = (std::size_t)(S.k0[s] + c) * S.plane + (std::size_t)(S.j0[s] + b) * S.px +
-                          (S.i0[s] + a);
+    const std::size_t o = (std::size_t)S.nm(S.i0[s] + a, S.j0[s] + b, S.k0[s] + c);
     const T* wm = S.wm + ((std::size_t)s * kMaxSrcWidth * kMaxSrcWidth * kMaxSrcWidth + t) * 6;
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
@@ -1023,7 +1085,7 @@ __global__ void energy_kernel(EnergyArgs<T> E) {
     };
     const double H = wgt(i, E.nq, E.w, E.m, E.h[0]) * wgt(j, E.nr, E.w, E.m, E.h[1]) *
                      wgt(k, E.ns, E.w, E.m, E.h[2]);
-    const std::size_t o = (std::size_t)k * E.plane + (std::size_t)j * E.px + i;
+    const std::size_t o = (std::size_t)E.nm(i, j, k);
     const double vx = E.q[o], vy = E.q[E.field + o], vz = E.q[2 * E.field + o];
     const double sxx = E.q[3 * E.field + o], syy = E.q[4 * E.field + o], szz = E.q[5 * E.field + o];
     const double sxy = E.q[6 * E.field + o], sxz = E.q[7 * E.field + o], syz = E.q[8 * E.field + o];

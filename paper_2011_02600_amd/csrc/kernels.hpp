@@ -17,6 +17,7 @@ struct StageArgs {
   const T* coef;      // 12 fields: M[xi][c] (3 xi + c), lambda/J, mu/J, 1/(rho J)
   const T* face;      // workspace base for the face coefficient arrays
   const int* bounds;  // tile bounds: q (nxt+1), r (nyt+1), s (nzc+1)
+  NodeMap nm;         // node -> element offset in a field
   std::size_t face_off[6];
   std::size_t face_n[6];
   std::size_t plane, field;
@@ -41,6 +42,7 @@ struct SourceArgs {
   T* dq;
   T* qout;       // may be null (RHS evaluation only)
   const T* wm;   // per source: width^3 nodes x 6 weights (w * M_c), padded to kMaxSrcWidth^3
+  NodeMap nm;
   std::size_t plane, field;
   int px, width;
   int i0[kMaxSources], j0[kMaxSources], k0[kMaxSources];
@@ -53,6 +55,7 @@ struct EnergyArgs {
   const T* q;
   const T* coef;
   double* part;
+  NodeMap nm;
   std::size_t plane, field;
   int px, nq, nr, ns, m;
   double h[3];
