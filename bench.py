@@ -7,9 +7,14 @@ plus the receiver gather.  Prints one JSON line.
     python bench.py [--gpus 1] [--steps 2000] [--warmup 20] [--no-cpu]
 
 The metric is Mpts*stage/s (grid points times Runge-Kutta stages per
-second); the roofline object reports the stage kernel's achieved algorithmic
-HBM bandwidth against the 8 TB/s peak; cpu_baseline times the CPU oracle on
-a bounded sample of the same workload.
+second).  A Runge-Kutta stage is two launches: the stage kernel over the
+tiled nodes (all but the last q column and r row) and the edge kernel over
+the rest.  The roofline object reports the stage kernel: algorithmic bytes
+of the nodes one launch computes over its average launch duration, timed by
+the library's events around each launch (sbp_set_profiling), against the
+8 TB/s HBM peak; `traffic` is the HBM bytes per launch from the committed
+rocprofv3 counter summary when that was taken on the current sources.
+cpu_baseline times the CPU oracle on a bounded sample of the same workload.
 """
 import argparse
 import hashlib
@@ -28,15 +33,20 @@ WORDS_STAGE1 = 9 + 12 + 9 + 9
 WORDS_STAGE = WORDS_STAGE1 + 9
 WORDS_AVG = (WORDS_STAGE1 + 4 * WORDS_STAGE) / 5.0
 PROFILE = os.path.join(ROOT, "profiles", "stage_kernel_topo_layer_257x257x193.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_2011_02600_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2011_02600_amd", "csrc")
 
 
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256 (16 hex digits) of the library sources: kernels, tiling and layout."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
-def read_traffic(nodes):
+def read_traffic():
     """HBM bytes per stage launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source (else None)."""
     if not os.path.exists(PROFILE):
@@ -151,8 +161,10 @@ def main():
     print("bench: %d steps in %.3f s (events) / %.3f s (wall)" % (args.steps, secs, wall), file=sys.stderr,
           flush=True)
 
-    # ---- stage kernel alone (same solver, no source, no receivers), events on
-    # the stream the kernels are launched on
+    # ---- the Runge-Kutta stage alone (same solver, no source, no receivers):
+    # events on the solver's stream around the steps (stage + edge kernel per
+    # stage), then the library's own events around every stage-kernel and
+    # edge-kernel launch (sbp_set_profiling)
     sbp.sbp_record(s.h, 0, None, None, 0)
     sbp.sbp_clear_sources(s.h)
     k0 = torch.cuda.Event(enable_timing=True)
@@ -162,10 +174,14 @@ def main():
     s.step(args.kernel_steps, dt)
     k1.record(stream)
     torch.cuda.synchronize()
-    launch_ms = k0.elapsed_time(k1) / (5 * args.kernel_steps)
-    bytes_per_launch = WORDS_AVG * 4 * nodes
+    rk_stage_ms = k0.elapsed_time(k1) / (5 * args.kernel_steps)
+    s.set_profiling(True)
+    s.step(args.kernel_steps // 4, dt)
+    launch_ms, edge_ms, nprof, stage_nodes = s.profile()
+    s.set_profiling(False)
+    bytes_per_launch = WORDS_AVG * 4 * stage_nodes
     achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9
-    traffic = read_traffic(nodes)
+    traffic = read_traffic()
     s.close()
 
     out = {
@@ -188,12 +204,16 @@ def main():
                    "launch": {"ty": args.ty, "zchunk": args.zchunk}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": None if traffic is None else round(traffic / (launch_ms / 1e3) / 1e9, 1),
-                     "traffic_bytes_per_launch": traffic,
+                     "traffic": None if traffic is None else int(traffic),
+                     "traffic_rate_gbs": None if traffic is None else round(traffic / (launch_ms / 1e3) / 1e9, 1),
                      "kernel": "stage_kernel<float,6,%d>" % args.ty,
                      "avg_launch_ms": round(launch_ms, 4),
+                     "launches_timed": nprof,
+                     "nodes_per_launch": stage_nodes,
                      "algorithmic_bytes_per_launch": int(bytes_per_launch),
-                     "words_per_node": WORDS_AVG},
+                     "words_per_node": WORDS_AVG,
+                     "edge_kernel_avg_launch_ms": round(edge_ms, 4),
+                     "rk_stage_ms": round(rk_stage_ms, 4)},
     }
     if not args.no_cpu:
         print("bench: cpu oracle baseline", file=sys.stderr, flush=True)

@@ -186,6 +186,21 @@ int sbp_energy(sbp_handle h, double* E);
  */
 int sbp_set_launch(sbp_handle h, int ty, int zchunk);
 
+/*
+ * Launch timing.  sbp_set_profiling(h, 1) resets the counters and from then
+ * on brackets every stage-kernel launch (one Runge-Kutta stage of the nodes
+ * covered by the tiles) and every edge-kernel launch (the remaining last q
+ * column and last r row) with HIP events on the handle's stream; the host
+ * waits for each stage to finish, so stepping is slower while it is on.
+ * sbp_set_profiling(h, 0) switches it off.  sbp_profile returns the average
+ * durations in milliseconds (*stage_ms, *edge_ms), the number of timed stages
+ * and the number of nodes one stage-kernel launch computes; any output
+ * pointer may be NULL.  Results are not changed by profiling.
+ */
+int sbp_set_profiling(sbp_handle h, int on);
+int sbp_profile(sbp_handle h, double* stage_ms, double* edge_ms, long long* nstages,
+                long long* stage_nodes);
+
 /* Current time and number of completed steps. */
 int sbp_time(sbp_handle h, double* t, long long* steps);
 

@@ -101,6 +101,11 @@ struct sbp_ctx {
   int nxt = 0, nyt = 0, nzc = 0;
   int ex = 0, ey = 0;   // last q column / last r row computed by the edge kernel
   bool bounds_dirty = true;
+  // launch timing (sbp_set_profiling)
+  bool prof = false;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  double prof_stage_ms = 0.0, prof_edge_ms = 0.0;
+  long long prof_n = 0;
 };
 
 namespace {
@@ -469,8 +474,20 @@ int run_stage(sbp_ctx* h, StageArgs<T>& a, int k, double dt, double tstage, bool
   a.Ak = rhs_only ? T(0) : (T)kRkA[k];
   a.Bk = rhs_only ? T(0) : (T)kRkB[k];
   a.dt = rhs_only ? T(1) : (T)dt;
+  if (h->prof) HIPCHK(hipEventRecord(h->ev[0], h->stream));
   HIPCHK(launch_stage<T>(h->order, h->ty, a, h->stream));
+  if (h->prof) HIPCHK(hipEventRecord(h->ev[1], h->stream));
   if (h->ex || h->ey) HIPCHK(launch_edge<T>(h->order, a, h->ex, h->ey, h->stream));
+  if (h->prof) {
+    HIPCHK(hipEventRecord(h->ev[2], h->stream));
+    HIPCHK(hipEventSynchronize(h->ev[2]));
+    float t01 = 0.f, t12 = 0.f;
+    HIPCHK(hipEventElapsedTime(&t01, h->ev[0], h->ev[1]));
+    HIPCHK(hipEventElapsedTime(&t12, h->ev[1], h->ev[2]));
+    h->prof_stage_ms += t01;
+    h->prof_edge_ms += t12;
+    ++h->prof_n;
+  }
   if (!h->src.empty()) {
     SourceArgs<T> s{};
     s.dq = dq;
@@ -861,7 +878,34 @@ int sbp_time(sbp_handle h, double* t, long long* steps) {
   return SBP_OK;
 }
 
+int sbp_set_profiling(sbp_handle h, int on) {
+  if (!h) return fail(SBP_EINVAL, "NULL handle");
+  if (on) {
+    for (int e = 0; e < 3; ++e)
+      if (!h->ev[e]) HIPCHK(hipEventCreate(&h->ev[e]));
+  }
+  h->prof = on != 0;
+  h->prof_stage_ms = h->prof_edge_ms = 0.0;
+  h->prof_n = 0;
+  return SBP_OK;
+}
+
+int sbp_profile(sbp_handle h, double* stage_ms, double* edge_ms, long long* nstages, long long* stage_nodes) {
+  if (!h) return fail(SBP_EINVAL, "NULL handle");
+  int rc = prepare_bounds(h);
+  if (rc) return rc;
+  const double n = h->prof_n > 0 ? (double)h->prof_n : 1.0;
+  if (stage_ms) *stage_ms = h->prof_stage_ms / n;
+  if (edge_ms) *edge_ms = h->prof_edge_ms / n;
+  if (nstages) *nstages = h->prof_n;
+  if (stage_nodes) *stage_nodes = (long long)(h->g.nq - h->ex) * (h->g.nr - h->ey) * h->g.ns;
+  return SBP_OK;
+}
+
 int sbp_destroy(sbp_handle h) {
+  if (h)
+    for (int e = 0; e < 3; ++e)
+      if (h->ev[e]) (void)hipEventDestroy(h->ev[e]);
   delete h;
   return SBP_OK;
 }

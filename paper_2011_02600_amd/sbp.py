@@ -53,6 +53,8 @@ def lib():
             "sbp_energy": [c_void_p, P(c_double)],
             "sbp_set_launch": [c_void_p, c_int, c_int],
             "sbp_time": [c_void_p, P(c_double), P(ctypes.c_longlong)],
+            "sbp_set_profiling": [c_void_p, c_int],
+            "sbp_profile": [c_void_p, P(c_double), P(c_double), P(ctypes.c_longlong), P(ctypes.c_longlong)],
             "sbp_destroy": [c_void_p],
         }
         for name, args in sig.items():
@@ -148,6 +150,19 @@ def sbp_set_launch(h, ty, zchunk):
     _check(lib().sbp_set_launch(h, int(ty), int(zchunk)))
 
 
+def sbp_set_profiling(h, on):
+    _check(lib().sbp_set_profiling(h, 1 if on else 0))
+
+
+def sbp_profile(h):
+    """(stage_ms, edge_ms, nstages, stage_nodes): average launch durations of
+    the stage and edge kernels since profiling was switched on."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    n, m = ctypes.c_longlong(), ctypes.c_longlong()
+    _check(lib().sbp_profile(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n), ctypes.byref(m)))
+    return a.value, b.value, n.value, m.value
+
+
 def sbp_time(h):
     t = ctypes.c_double(0)
     n = ctypes.c_longlong(0)
@@ -241,6 +256,12 @@ class Solver:
 
     def set_launch(self, ty=8, zchunk=0):
         sbp_set_launch(self.h, ty, zchunk)
+
+    def set_profiling(self, on=True):
+        sbp_set_profiling(self.h, on)
+
+    def profile(self):
+        return sbp_profile(self.h)
 
     def time(self):
         return sbp_time(self.h)
