@@ -5,6 +5,7 @@ One step = five Runge-Kutta stages of the full semi-discrete right-hand side
 plus the receiver gather.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps 2000] [--warmup 20] [--no-cpu]
+    python bench.py --workload batched [--steps 100] [--warmup 5]
 
 The metric is Mpts*stage/s (grid points times Runge-Kutta stages per
 second).  A Runge-Kutta stage is two launches: the stage kernel over the
@@ -15,6 +16,10 @@ the library's events around each launch (sbp_set_profiling), against the
 8 TB/s HBM peak; `traffic` is the HBM bytes per launch from the committed
 rocprofv3 counter summary when that was taken on the current sources.
 cpu_baseline times the CPU oracle on a bounded sample of the same workload.
+
+`--workload batched` measures the batched-shots workload instead (32 cubes
+of uneven size, orders 4 and 6, one sbp_step_batch call): shots per second
+for `steps` steps per shot, beside the same shots stepped one after another.
 """
 import argparse
 import hashlib
@@ -92,6 +97,75 @@ def cpu_baseline(wl, nstages=2):
                       "%.1f s; mesh/metric setup excluded" % ((nstages,) + tuple(Q.shape[1:][::-1]) + (el,))}
 
 
+def run_batched(args, W, sbp, torch, np, dev):
+    steps = args.steps if args.steps != 2000 else 100
+    warm = args.warmup if args.warmup != 20 else 5
+    print("bench: generating 32 shots", file=sys.stderr, flush=True)
+    shots = W.batched_shots(32)
+    solvers = []
+    for n, sh in enumerate(shots):
+        s = sbp.Solver(sh["xyz"], order=sh["order"], dtype="f32", gamma=sh["gamma"], device=dev)
+        s.set_material(sh["rho"], sh["cp"], sh["cs"])
+        s.add_source(sh["src_xi"], sh["src_M"], sbp.SBP_STF_RICKER, sh["src_f0"], sh["src_t0"])
+        s.record(sh["receivers"], 2 * (warm + steps))
+        solvers.append(s)
+        print("bench: shot %d: %d^3 order %d" % (n, sh["xyz"].shape[1], sh["order"]), file=sys.stderr, flush=True)
+    hs = [s.h for s in solvers]
+    dts = [sh["dt"] for sh in shots]
+    stream = solvers[0].stream
+    points = sum(int(np.prod(sh["xyz"].shape[1:])) for sh in shots)
+    sbp.sbp_step_batch(hs, warm, dts)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sbp.sbp_step_batch(hs, steps, dts)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    batch_ms = e0.elapsed_time(e1)
+    print("bench: batched %d steps in %.1f ms" % (steps, batch_ms), file=sys.stderr, flush=True)
+    # the same shots one after another, each with its own sbp_step call
+    e0.record(stream)
+    for s, d in zip(solvers, dts):
+        s.step(steps, d)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    seq_ms = e0.elapsed_time(e1)
+    print("bench: one by one %d steps in %.1f ms" % (steps, seq_ms), file=sys.stderr, flush=True)
+    for s in solvers:
+        if not np.all(np.isfinite(s.traces.float().cpu().numpy())):
+            raise RuntimeError("non-finite receiver traces")
+        s.close()
+    secs = batch_ms / 1e3
+    bytes_stage = WORDS_AVG * 4 * points
+    out = {
+        "metric": "shots/s (batched shots, %d steps per shot)" % steps,
+        "value": round(len(shots) / secs, 3),
+        "unit": "shots/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": round(batch_ms / steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched_shots: 32 cubes of 65^3..193^3 points (seeded sizes), orders 4/6 "
+                               "alternating, Gaussian-random-field media (10-cell correlation, +-10 %), "
+                               "Ricker moment source, 16 surface receivers each, CFL 0.5",
+                   "sizes": [int(sh["xyz"].shape[1]) for sh in shots],
+                   "orders": [sh["order"] for sh in shots], "points": points},
+        "mpts_stage_per_s": round(points * 5 * steps / secs / 1e6, 1),
+        "one_by_one": {"ms": round(seq_ms, 2), "shots_per_s": round(len(shots) / (seq_ms / 1e3), 3),
+                       "batch_speedup": round(seq_ms / batch_ms, 3)},
+        "stage_rate": {"scope": "whole Runge-Kutta stage of all shots (stage, edge and source kernels)",
+                       "algorithmic_gbs": round(bytes_stage * 5 * steps / secs / 1e9, 1),
+                       "frac_of_peak": round(bytes_stage * 5 * steps / secs / 1e9 / PEAK_HBM_GBS, 4)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +176,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ty", type=int, default=8)
     ap.add_argument("--zchunk", type=int, default=0)
+    ap.add_argument("--workload", default="topo_layer", choices=["topo_layer", "batched"])
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (x4) for HBM counter calibration")
     args = ap.parse_args()
@@ -126,6 +201,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read_per_copy": 4 * n, "copies": 4}))
+        return
+    if args.workload == "batched":
+        run_batched(args, W, sbp, torch, np, dev)
         return
     print("bench: generating workload", file=sys.stderr, flush=True)
     wl = W.topo_layer()

@@ -164,6 +164,20 @@ int sbp_record(sbp_handle h, int nrec, const int* ijk, void* out_device, int max
 int sbp_step(sbp_handle h, int nsteps, double dt);
 
 /*
+ * Advance n handles (1 <= n <= 64) by nsteps steps each, handle i with step
+ * dt[i] (host array of n doubles), in shared launches: per Runge-Kutta
+ * stage one stage-kernel and one edge-kernel launch for all handles of the
+ * same order and tile height, one launch for all their point sources, and
+ * one receiver launch per step.  Each handle's state, time, step count and
+ * receiver traces end up bitwise as after sbp_step(hs[i], nsteps, dt[i]).
+ * All handles need the same dtype and the same stream, distinct handles and
+ * a medium; the argument tables live in hs[0]'s workspace.  Synchronises the
+ * stream before returning.  Batched stepping of many independent sources or
+ * media ("shots") on grids of uneven size.
+ */
+int sbp_step_batch(sbp_handle* hs, int n, int nsteps, const double* dt);
+
+/*
  * Evaluate the semi-discrete right-hand side dQ/dt of the current state at
  * time t (sources evaluated at t) into out_device (9 dense grid functions,
  * handle dtype).  The state and the time are not changed.  Asynchronous.

@@ -49,6 +49,12 @@ const double kRkC[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 
                         2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
 
 constexpr int kMaxRec = 65536;
+// sbp_step_batch: at most kMaxBatch handles; per-step tables are uploaded for
+// kBatchSteps steps at a time; handles are grouped by (order, tile height)
+constexpr int kMaxBatch = 64;
+constexpr int kBatchSteps = 32;
+constexpr int kMaxGroups = 6;
+
 constexpr int kMaxPart = 1024;
 constexpr double kPi = 3.14159265358979323846;
 
@@ -80,7 +86,7 @@ struct sbp_ctx {
   std::size_t ws_bytes = 0;
   // byte offsets in the workspace
   std::size_t off_qa = 0, off_qb = 0, off_dq = 0, off_coef = 0, off_face[6] = {}, off_src = 0,
-              off_rec = 0, off_part = 0, off_bounds = 0, off_tab = 0, total = 0;
+              off_rec = 0, off_part = 0, off_bounds = 0, off_tab = 0, off_batch = 0, total = 0;
   std::size_t face_n[6] = {};
   int px = 0;
   std::size_t plane = 0, field = 0;
@@ -123,6 +129,30 @@ int check_dims(int nq, int nr, int ns, int order, int dtype) {
   return SBP_OK;
 }
 
+// Tables of sbp_step_batch, in the workspace of the first handle of a batch
+// (sized for double, the larger argument blocks).
+struct BatchRegion {
+  std::size_t stage, first, src, src_first, rec, rec_first, total;
+};
+BatchRegion batch_region() {
+  BatchRegion r{};
+  std::size_t o = 0;
+  auto take = [&](std::size_t bytes) {
+    std::size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  r.stage = take((std::size_t)10 * kMaxBatch * sizeof(StageArgs<double>));
+  r.first = take((std::size_t)2 * kMaxGroups * (kMaxBatch + 1) * sizeof(int));
+  r.src = take((std::size_t)kBatchSteps * 5 * kMaxBatch * sizeof(SourceArgs<double>));
+  r.src_first = take((std::size_t)(kMaxBatch + 1) * sizeof(int));
+  r.rec = take((std::size_t)kBatchSteps * kMaxBatch * sizeof(RecordArgs<double>));
+  r.rec_first = take((std::size_t)(kMaxBatch + 1) * sizeof(int));
+  r.total = o;
+  return r;
+}
+std::size_t batch_region_bytes() { return batch_region().total; }
+
 void layout(sbp_ctx* h) {
   const int es = h->esize;
   const Geometry& g = h->g;
@@ -159,6 +189,7 @@ void layout(sbp_ctx* h) {
   h->off_part = take(kMaxPart * sizeof(double));
   h->off_bounds = take((std::size_t)(g.nq + g.nr + g.ns + 16) * sizeof(int));
   h->off_tab = take((std::size_t)kClosureTab * kMaxM * kMaxCols * es);
+  h->off_batch = take(batch_region_bytes());
   h->total = o;
 }
 
@@ -446,6 +477,8 @@ StageArgs<T> stage_args(sbp_ctx* h) {
   }
   a.bounds = (const int*)(h->ws + h->off_bounds);
   a.nm = h->nm;
+  a.ex = h->ex;
+  a.ey = h->ey;
   a.plane = h->plane;
   a.field = h->field;
   a.px = h->px;
@@ -464,20 +497,53 @@ StageArgs<T> stage_args(sbp_ctx* h) {
   return a;
 }
 
+// point sources of stage k at time tstage (g(t) evaluated on the host in double)
+template <typename T>
+SourceArgs<T> source_args(sbp_ctx* h, int k, double dt, double tstage, bool rhs_only, T* qout) {
+  SourceArgs<T> s{};
+  s.dq = (T*)(h->ws + h->off_dq);
+  s.qout = rhs_only ? nullptr : qout;
+  s.wm = (const T*)(h->ws + h->off_src);
+  s.nm = h->nm;
+  s.plane = h->plane;
+  s.field = h->field;
+  s.px = h->px;
+  s.width = h->width;
+  s.Bk = rhs_only ? T(0) : (T)kRkB[k];
+  for (std::size_t i = 0; i < h->src.size(); ++i) {
+    s.i0[i] = h->src[i].i0;
+    s.j0[i] = h->src[i].j0;
+    s.k0[i] = h->src[i].k0;
+    s.gdt[i] = (T)((rhs_only ? 1.0 : dt) * stf_value(h->src[i], tstage));
+  }
+  return s;
+}
+
+// arguments of Runge-Kutta stage k (or of the right-hand side alone) with the
+// input state in Q_b (c = 1) or Q_a (c = 0)
+template <typename T>
+StageArgs<T> stage_entry(sbp_ctx* h, const StageArgs<T>& a, int k, int c, double dt, bool rhs_only) {
+  StageArgs<T> b = a;
+  T* qa = (T*)(h->ws + h->off_qa);
+  T* qb = (T*)(h->ws + h->off_qb);
+  b.qin = c ? qb : qa;
+  b.qout = c ? qa : qb;
+  b.dq = (T*)(h->ws + h->off_dq);
+  b.read_dq = (!rhs_only && k > 0) ? 1 : 0;
+  b.Ak = rhs_only ? T(0) : (T)kRkA[k];
+  b.Bk = rhs_only ? T(0) : (T)kRkB[k];
+  b.dt = rhs_only ? T(1) : (T)dt;
+  return b;
+}
+
 template <typename T>
 int run_stage(sbp_ctx* h, StageArgs<T>& a, int k, double dt, double tstage, bool rhs_only, T* qin, T* qout) {
-  T* dq = (T*)(h->ws + h->off_dq);
-  a.qin = qin;
-  a.qout = qout;
-  a.dq = dq;
-  a.read_dq = (!rhs_only && k > 0) ? 1 : 0;
-  a.Ak = rhs_only ? T(0) : (T)kRkA[k];
-  a.Bk = rhs_only ? T(0) : (T)kRkB[k];
-  a.dt = rhs_only ? T(1) : (T)dt;
+  const int c = qin == (T*)(h->ws + h->off_qb) ? 1 : 0;
+  a = stage_entry<T>(h, a, k, c, dt, rhs_only);
   if (h->prof) HIPCHK(hipEventRecord(h->ev[0], h->stream));
   HIPCHK(launch_stage<T>(h->order, h->ty, a, h->stream));
   if (h->prof) HIPCHK(hipEventRecord(h->ev[1], h->stream));
-  if (h->ex || h->ey) HIPCHK(launch_edge<T>(h->order, a, h->ex, h->ey, h->stream));
+  if (h->ex || h->ey) HIPCHK(launch_edge<T>(h->order, a, h->stream));
   if (h->prof) {
     HIPCHK(hipEventRecord(h->ev[2], h->stream));
     HIPCHK(hipEventSynchronize(h->ev[2]));
@@ -489,22 +555,7 @@ int run_stage(sbp_ctx* h, StageArgs<T>& a, int k, double dt, double tstage, bool
     ++h->prof_n;
   }
   if (!h->src.empty()) {
-    SourceArgs<T> s{};
-    s.dq = dq;
-    s.qout = rhs_only ? nullptr : qout;
-    s.wm = (const T*)(h->ws + h->off_src);
-    s.nm = h->nm;
-    s.plane = h->plane;
-    s.field = h->field;
-    s.px = h->px;
-    s.width = h->width;
-    s.Bk = rhs_only ? T(0) : (T)kRkB[k];
-    for (std::size_t i = 0; i < h->src.size(); ++i) {
-      s.i0[i] = h->src[i].i0;
-      s.j0[i] = h->src[i].j0;
-      s.k0[i] = h->src[i].k0;
-      s.gdt[i] = (T)((rhs_only ? 1.0 : dt) * stf_value(h->src[i], tstage));
-    }
+    const SourceArgs<T> s = source_args<T>(h, k, dt, tstage, rhs_only, qout);
     HIPCHK(launch_source<T>(s, (int)h->src.size(), h->stream));
   }
   return SBP_OK;
@@ -536,6 +587,166 @@ int do_steps(sbp_ctx* h, int nsteps, double dt) {
     ++h->steps;
   }
   h->t = t0 + nsteps * dt;
+  return SBP_OK;
+}
+
+// Several handles advanced together: the same kernels and per-grid
+// arguments as do_steps, but each launch covers the tiles of all grids of
+// one (order, tile height) group.  Results are bitwise those of do_steps.
+template <typename T>
+int do_steps_batch(sbp_ctx** hs, int n, int nsteps, const double* dt) {
+  sbp_ctx* h0 = hs[0];
+  hipStream_t st = h0->stream;
+  const BatchRegion R = batch_region();
+  char* base = h0->ws + h0->off_batch;
+  for (int g = 0; g < n; ++g) {
+    int rc = prepare_bounds(hs[g]);
+    if (rc) return rc;
+  }
+  // groups: handles sorted by (order, tile height)
+  std::vector<int> ord(n);
+  for (int g = 0; g < n; ++g) ord[g] = g;
+  auto key = [&](int g) { return hs[g]->order * 100 + hs[g]->ty; };
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return key(a) < key(b); });
+  std::vector<int> gstart{0};
+  for (int p = 1; p < n; ++p)
+    if (key(ord[p]) != key(ord[p - 1])) gstart.push_back(p);
+  const int ngroups = (int)gstart.size();
+  gstart.push_back(n);
+  if (ngroups > kMaxGroups) return fail(SBP_EINVAL, "too many (order, tile height) groups in a batch");
+  // stage argument tables (5 stages x 2 ping-pong parities) and block prefixes
+  std::vector<StageArgs<T>> sa((std::size_t)10 * kMaxBatch);
+  std::vector<int> firsts((std::size_t)2 * kMaxGroups * (kMaxBatch + 1), 0);
+  std::vector<int> sblocks(ngroups), eblocks(ngroups);
+  bool buf_ok = true;
+  for (int G = 0; G < ngroups; ++G) {
+    int* fs = firsts.data() + (std::size_t)(2 * G) * (kMaxBatch + 1);
+    int* fe = firsts.data() + (std::size_t)(2 * G + 1) * (kMaxBatch + 1);
+    int ts = 0, te = 0;
+    for (int p = gstart[G]; p < gstart[G + 1]; ++p) {
+      sbp_ctx* h = hs[ord[p]];
+      StageArgs<T> a = stage_args<T>(h);
+      for (int k = 0; k < 5; ++k)
+        for (int P = 0; P < 2; ++P)
+          sa[(std::size_t)(k * 2 + P) * kMaxBatch + p] = stage_entry<T>(h, a, k, h->cur ^ P, dt[ord[p]], false);
+      const int q = p - gstart[G];
+      fs[q] = ts;
+      fe[q] = te;
+      ts += a.ntiles;
+      te += edge_blocks(a);
+      buf_ok = buf_ok && 12.0 * (double)a.field * sizeof(T) < 4294967296.0;
+    }
+    fs[gstart[G + 1] - gstart[G]] = ts;
+    fe[gstart[G + 1] - gstart[G]] = te;
+    sblocks[G] = ts;
+    eblocks[G] = te;
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipMemcpyAsync(base + R.stage, sa.data(), sa.size() * sizeof(StageArgs<T>), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(base + R.first, firsts.data(), firsts.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  // handles with sources / receivers (compacted, in batch order)
+  std::vector<int> withsrc, withrec;
+  for (int g = 0; g < n; ++g) {
+    if (!hs[g]->src.empty()) withsrc.push_back(g);
+    if (hs[g]->nrec > 0) withrec.push_back(g);
+  }
+  std::vector<int> sfirst(withsrc.size() + 1, 0), rfirst(withrec.size() + 1, 0);
+  for (std::size_t q = 0; q < withsrc.size(); ++q) sfirst[q + 1] = sfirst[q] + (int)hs[withsrc[q]]->src.size();
+  for (std::size_t q = 0; q < withrec.size(); ++q) rfirst[q + 1] = rfirst[q] + hs[withrec[q]]->nrec;
+  HIPCHK(hipMemcpyAsync(base + R.src_first, sfirst.data(), sfirst.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(base + R.rec_first, rfirst.data(), rfirst.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  const StageArgs<T>* dsa = (const StageArgs<T>*)(base + R.stage);
+  const int* dfirst = (const int*)(base + R.first);
+
+  std::vector<double> t0(n);
+  for (int g = 0; g < n; ++g) t0[g] = hs[g]->t;
+  std::vector<SourceArgs<T>> stab;
+  std::vector<RecordArgs<T>> rtab;
+  for (int n0 = 0; n0 < nsteps; n0 += kBatchSteps) {
+    const int nc = std::min(kBatchSteps, nsteps - n0);
+    // the previous chunk's kernels and table copies are done before its host
+    // and device tables are overwritten
+    HIPCHK(hipStreamSynchronize(st));
+    // per-step source and receiver tables of this chunk
+    stab.assign((std::size_t)nc * 5 * std::max<std::size_t>(1, withsrc.size()), SourceArgs<T>{});
+    rtab.assign((std::size_t)nc * std::max<std::size_t>(1, withrec.size()), RecordArgs<T>{});
+    for (std::size_t q = 0; q < withsrc.size(); ++q) {
+      sbp_ctx* h = hs[withsrc[q]];
+      const double d = dt[withsrc[q]];
+      for (int nn = 0; nn < nc; ++nn) {
+        const int step = n0 + nn;
+        const double tn = t0[withsrc[q]] + step * d;
+        for (int k = 0; k < 5; ++k) {
+          const int c = h->cur ^ ((step * 5 + k) & 1);
+          T* qout = (T*)(h->ws + (c ? h->off_qa : h->off_qb));
+          stab[((std::size_t)nn * 5 + k) * withsrc.size() + q] = source_args<T>(h, k, d, tn + kRkC[k] * d, false, qout);
+        }
+      }
+    }
+    for (std::size_t q = 0; q < withrec.size(); ++q) {
+      sbp_ctx* h = hs[withrec[q]];
+      for (int nn = 0; nn < nc; ++nn) {
+        const int step = n0 + nn;
+        const int c = h->cur ^ (((step + 1) * 5) & 1);  // state after the step
+        RecordArgs<T> r{};
+        r.q = (const T*)(h->ws + (c ? h->off_qb : h->off_qa));
+        r.field = h->field;
+        r.off = (const long long*)(h->ws + h->off_rec);
+        r.out = (T*)h->rec_out + (std::size_t)(h->rec_step + step) * h->nrec * 3;
+        rtab[(std::size_t)nn * withrec.size() + q] = r;
+      }
+    }
+    if (!withsrc.empty())
+      HIPCHK(hipMemcpyAsync(base + R.src, stab.data(), stab.size() * sizeof(SourceArgs<T>), hipMemcpyHostToDevice,
+                            st));
+    if (!withrec.empty())
+      HIPCHK(hipMemcpyAsync(base + R.rec, rtab.data(), rtab.size() * sizeof(RecordArgs<T>), hipMemcpyHostToDevice,
+                            st));
+    for (int nn = 0; nn < nc; ++nn) {
+      const int step = n0 + nn;
+      for (int k = 0; k < 5; ++k) {
+        const int P = (step * 5 + k) & 1;
+        for (int G = 0; G < ngroups; ++G) {
+          BatchArgs<T> b{};
+          b.args = dsa + (std::size_t)(k * 2 + P) * kMaxBatch + gstart[G];
+          b.n = gstart[G + 1] - gstart[G];
+          b.first = dfirst + (std::size_t)(2 * G) * (kMaxBatch + 1);
+          b.total = sblocks[G];
+          sbp_ctx* hg = hs[ord[gstart[G]]];
+          HIPCHK(launch_stage_batch<T>(hg->order, hg->ty, b, buf_ok, st));
+          b.first = dfirst + (std::size_t)(2 * G + 1) * (kMaxBatch + 1);
+          b.total = eblocks[G];
+          HIPCHK(launch_edge_batch<T>(hg->order, b, st));
+        }
+        if (!withsrc.empty()) {
+          SourceBatch<T> sb{};
+          sb.args = (const SourceArgs<T>*)(base + R.src) + ((std::size_t)nn * 5 + k) * withsrc.size();
+          sb.first = (const int*)(base + R.src_first);
+          sb.n = (int)withsrc.size();
+          sb.total = sfirst.back();
+          HIPCHK(launch_source_batch<T>(sb, st));
+        }
+      }
+      if (!withrec.empty()) {
+        RecordBatch<T> rb{};
+        rb.args = (const RecordArgs<T>*)(base + R.rec) + (std::size_t)nn * withrec.size();
+        rb.first = (const int*)(base + R.rec_first);
+        rb.n = (int)withrec.size();
+        rb.total = rfirst.back();
+        HIPCHK(launch_record_batch<T>(rb, st));
+      }
+    }
+  }
+  // host-side state of every handle, as after nsteps calls of do_steps
+  for (int g = 0; g < n; ++g) {
+    sbp_ctx* h = hs[g];
+    h->cur ^= (5 * nsteps) & 1;
+    h->steps += nsteps;
+    if (h->nrec > 0) h->rec_step += nsteps;
+    h->t = t0[g] + nsteps * dt[g];
+  }
+  // the tables are read by kernels still in flight: keep them until done
+  HIPCHK(hipStreamSynchronize(st));
   return SBP_OK;
 }
 
@@ -846,6 +1057,28 @@ int sbp_step(sbp_handle h, int nsteps, double dt) {
     return fail(SBP_EINVAL, "receiver buffer holds %d steps; %lld recorded, %d requested", h->rec_max,
                 h->rec_step, nsteps);
   return h->dtype == SBP_F32 ? do_steps<float>(h, nsteps, dt) : do_steps<double>(h, nsteps, dt);
+}
+
+int sbp_step_batch(sbp_handle* hs, int n, int nsteps, const double* dt) {
+  if (!hs || !dt) return fail(SBP_EINVAL, "NULL argument");
+  if (n < 1 || n > kMaxBatch) return fail(SBP_EINVAL, "n must be in [1, %d]", kMaxBatch);
+  if (nsteps < 0) return fail(SBP_EINVAL, "need nsteps >= 0");
+  for (int g = 0; g < n; ++g) {
+    sbp_ctx* h = hs[g];
+    if (!h) return fail(SBP_EINVAL, "NULL handle in batch (%d)", g);
+    for (int e = 0; e < g; ++e)
+      if (hs[e] == h) return fail(SBP_EINVAL, "handle %d appears twice in the batch", g);
+    if (h->dtype != hs[0]->dtype) return fail(SBP_EINVAL, "all handles of a batch need the same dtype");
+    if (h->stream != hs[0]->stream) return fail(SBP_EINVAL, "all handles of a batch need the same stream");
+    if (!h->have_material) return fail(SBP_ESTATE, "sbp_set_material has not been called (handle %d)", g);
+    if (!(dt[g] > 0) || !std::isfinite(dt[g])) return fail(SBP_EINVAL, "need dt > 0 (handle %d)", g);
+    if (h->nrec > 0 && h->rec_step + nsteps > h->rec_max)
+      return fail(SBP_EINVAL, "receiver buffer of handle %d holds %d steps; %lld recorded, %d requested", g,
+                  h->rec_max, h->rec_step, nsteps);
+  }
+  if (nsteps == 0) return SBP_OK;
+  return hs[0]->dtype == SBP_F32 ? do_steps_batch<float>(hs, n, nsteps, dt)
+                                 : do_steps_batch<double>(hs, n, nsteps, dt);
 }
 
 int sbp_rhs(sbp_handle h, void* out_device, double t) {

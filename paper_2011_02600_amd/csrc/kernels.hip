@@ -206,7 +206,7 @@ __device__ __forceinline__ void node_rates(const T u[3][3], const T dv[3], const
 #define SBP_STAGE_MIN_WAVES 1  // minimum waves per SIMD the register allocation must allow
 #endif
 template <typename T, int ORDER, int TY, bool BUF>
-__global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(const StageArgs<T> A) {
+__device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile) {
   using S = Stencil<ORDER>;
   constexpr int R = S::R, Q = S::Q, M = S::M;
   constexpr int H = Q;            // halo width (Q >= R)
@@ -245,9 +245,6 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
   constexpr int KF = FL ? (NFE + NT - 1) / NT : 1;
   __shared__ T lface[FL ? NFE : 1];
 
-  // XCD-aware tile order: consecutive tiles land on the same XCD
-  const int per = gridDim.x >> 3;
-  const int tile = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   if (tile >= A.ntiles) return;
   const int xt = tile % A.nxt;
   const int yt = (tile / A.nxt) % A.nyt;
@@ -786,7 +783,7 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
 // interior stencil, boundary rows from the closure table, fluxes by flux3,
 // rates by node_rates, penalties by face_penalty, then the Runge-Kutta update.
 template <typename T, int ORDER, int KZ>
-__global__ __launch_bounds__(64 * KZ) void edge_kernel(const StageArgs<T> A, int ex, int ey) {
+__device__ __forceinline__ void edge_body(const StageArgs<T>& A, int b) {
   using S = Stencil<ORDER>;
   constexpr int R = S::R, Q = S::Q, M = S::M;
   constexpr int QD = R + Q + 1;
@@ -803,6 +800,7 @@ __global__ __launch_bounds__(64 * KZ) void edge_kernel(const StageArgs<T> A, int
   __shared__ T lqc[6 * NT];
 
   const int nq = A.nq, nr = A.nr, ns = A.ns;
+  const int ex = A.ex, ey = A.ey;
   const int tid = threadIdx.y * 64 + threadIdx.x;
   for (int e = tid; e < kClosureTab * TABN; e += NT) ltab[e] = A.tab[e];
 
@@ -811,7 +809,6 @@ __global__ __launch_bounds__(64 * KZ) void edge_kernel(const StageArgs<T> A, int
   const int ntc = ex ? (nr + 63) / 64 : 0;               // column strip tiles along r
   const int nrow = nq - (ex ? 1 : 0);                     // row strip points along q
   const int ntr = ey ? (nrow + 63) / 64 : 0;
-  int b = blockIdx.x;
   if (b >= (ntc + ntr) * nkt) return;
   const int st = b < ntc * nkt ? 0 : 1;                   // 0: column strip, 1: row strip
   if (st == 1) b -= ntc * nkt;
@@ -1037,10 +1034,57 @@ __global__ __launch_bounds__(64 * KZ) void edge_kernel(const StageArgs<T> A, int
 }
 
 // ---------------------------------------------------------------------------
+// launch wrappers: one grid with its arguments passed by value (stage_kernel,
+// edge_kernel), or the blocks of many grids in one launch (the _batch
+// kernels: block -> (grid, local block) through the prefix sums of the
+// per-grid block counts; the grid's arguments are read from a device table)
+template <typename T, int ORDER, int TY, bool BUF>
+__global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(const StageArgs<T> A) {
+  // XCD-aware tile order: consecutive tiles land on the same XCD
+  const int per = gridDim.x >> 3;
+  stage_body<T, ORDER, TY, BUF>(A, (blockIdx.x & 7) * per + (blockIdx.x >> 3));
+}
+
+template <typename T, int ORDER, int KZ>
+__global__ __launch_bounds__(64 * KZ) void edge_kernel(const StageArgs<T> A) {
+  edge_body<T, ORDER, KZ>(A, blockIdx.x);
+}
+
+// last entry of first[0 .. n-1] (non-decreasing, first[0] = 0) that is <= item
+__device__ __forceinline__ int batch_find(const int* __restrict__ first, int n, int item) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first[mid] <= item) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T, int ORDER, int TY, bool BUF>
+__global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel_batch(const BatchArgs<T> B) {
+  const int per = gridDim.x >> 3;
+  const int item = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (item >= B.total) return;
+  const int g = batch_find(B.first, B.n, item);
+  // a private copy: loaded once, and no store of the kernel can alias it
+  const StageArgs<T> A = B.args[g];
+  stage_body<T, ORDER, TY, BUF>(A, item - B.first[g]);
+}
+
+template <typename T, int ORDER, int KZ>
+__global__ __launch_bounds__(64 * KZ) void edge_kernel_batch(const BatchArgs<T> B) {
+  const int item = blockIdx.x;
+  if (item >= B.total) return;
+  const int g = batch_find(B.first, B.n, item);
+  const StageArgs<T> A = B.args[g];
+  edge_body<T, ORDER, KZ>(A, item - B.first[g]);
+}
+
+// ---------------------------------------------------------------------------
 // point sources: dQ += gdt * w M, Q_out += Bk * gdt * w M on the source stencil
 template <typename T>
-__global__ void source_kernel(SourceArgs<T> S) {
-  const int s = blockIdx.x;
+__device__ __forceinline__ void source_body(const SourceArgs<T>& S, const int s) {
   const int w = S.width;
   const int n = w * w * w;
   for (int t = threadIdx.x; t < n; t += blockDim.x) {
@@ -1054,6 +1098,32 @@ __global__ void source_kernel(SourceArgs<T> S) {
       if (S.qout) S.qout[(3 + f) * S.field + o] += S.Bk * add;
     }
   }
+}
+
+template <typename T>
+__global__ void source_kernel(SourceArgs<T> S) {
+  source_body(S, blockIdx.x);
+}
+
+template <typename T>
+__global__ void source_kernel_batch(const SourceBatch<T> B) {
+  const int item = blockIdx.x;
+  if (item >= B.total) return;
+  const int g = batch_find(B.first, B.n, item);
+  source_body(B.args[g], item - B.first[g]);
+}
+
+// receivers of several grids: one thread per receiver
+template <typename T>
+__global__ void record_kernel_batch(const RecordBatch<T> B) {
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= B.total) return;
+  const int g = batch_find(B.first, B.n, item);
+  const RecordArgs<T>& R = B.args[g];
+  const int r = item - B.first[g];
+  const long long o = R.off[r];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) R.out[(std::size_t)r * 3 + c] = R.q[c * R.field + o];
 }
 
 // receivers: out[(step * nrec + r) * 3 + c] = v_c(node_r)
@@ -1138,19 +1208,83 @@ hipError_t launch_stage(int order, int ty, const StageArgs<T>& a, hipStream_t st
 }
 
 template <typename T>
-hipError_t launch_edge(int order, const StageArgs<T>& a, int ex, int ey, hipStream_t st) {
+int edge_blocks(const StageArgs<T>& a) {
   constexpr int KZ = 8;
   const int nkt = (a.ns + KZ - 1) / KZ;
-  const int nb = ((ex ? (a.nr + 63) / 64 : 0) + (ey ? (a.nq - (ex ? 1 : 0) + 63) / 64 : 0)) * nkt;
+  return ((a.ex ? (a.nr + 63) / 64 : 0) + (a.ey ? (a.nq - (a.ex ? 1 : 0) + 63) / 64 : 0)) * nkt;
+}
+
+template <typename T>
+hipError_t launch_edge(int order, const StageArgs<T>& a, hipStream_t st) {
+  constexpr int KZ = 8;
+  const int nb = edge_blocks(a);
   if (nb == 0) return hipSuccess;
   if (order == 2)
-    hipLaunchKernelGGL((edge_kernel<T, 2, KZ>), dim3(nb), dim3(64, KZ), 0, st, a, ex, ey);
+    hipLaunchKernelGGL((edge_kernel<T, 2, KZ>), dim3(nb), dim3(64, KZ), 0, st, a);
   else if (order == 4)
-    hipLaunchKernelGGL((edge_kernel<T, 4, KZ>), dim3(nb), dim3(64, KZ), 0, st, a, ex, ey);
+    hipLaunchKernelGGL((edge_kernel<T, 4, KZ>), dim3(nb), dim3(64, KZ), 0, st, a);
   else if (order == 6)
-    hipLaunchKernelGGL((edge_kernel<T, 6, KZ>), dim3(nb), dim3(64, KZ), 0, st, a, ex, ey);
+    hipLaunchKernelGGL((edge_kernel<T, 6, KZ>), dim3(nb), dim3(64, KZ), 0, st, a);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename T, int ORDER, int TY>
+static hipError_t launch_stage_batch_t(const BatchArgs<T>& b, bool buf, hipStream_t st) {
+  if constexpr (sizeof(T) == 8 && TY == 16) {
+    return hipErrorInvalidValue;
+  } else {
+    const int nb = ((b.total + 7) / 8) * 8;
+    if (buf)
+      hipLaunchKernelGGL((stage_kernel_batch<T, ORDER, TY, true>), dim3(nb), dim3(64, TY), 0, st, b);
+    else
+      hipLaunchKernelGGL((stage_kernel_batch<T, ORDER, TY, false>), dim3(nb), dim3(64, TY), 0, st, b);
+    return hipGetLastError();
+  }
+}
+
+template <typename T>
+hipError_t launch_stage_batch(int order, int ty, const BatchArgs<T>& b, bool buf, hipStream_t st) {
+  if (b.total == 0) return hipSuccess;
+  if (ty == 16 && sizeof(T) == 4) {
+    if (order == 2) return launch_stage_batch_t<T, 2, 16>(b, buf, st);
+    if (order == 4) return launch_stage_batch_t<T, 4, 16>(b, buf, st);
+    if (order == 6) return launch_stage_batch_t<T, 6, 16>(b, buf, st);
+  } else {
+    if (order == 2) return launch_stage_batch_t<T, 2, 8>(b, buf, st);
+    if (order == 4) return launch_stage_batch_t<T, 4, 8>(b, buf, st);
+    if (order == 6) return launch_stage_batch_t<T, 6, 8>(b, buf, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_edge_batch(int order, const BatchArgs<T>& b, hipStream_t st) {
+  constexpr int KZ = 8;
+  if (b.total == 0) return hipSuccess;
+  if (order == 2)
+    hipLaunchKernelGGL((edge_kernel_batch<T, 2, KZ>), dim3(b.total), dim3(64, KZ), 0, st, b);
+  else if (order == 4)
+    hipLaunchKernelGGL((edge_kernel_batch<T, 4, KZ>), dim3(b.total), dim3(64, KZ), 0, st, b);
+  else if (order == 6)
+    hipLaunchKernelGGL((edge_kernel_batch<T, 6, KZ>), dim3(b.total), dim3(64, KZ), 0, st, b);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_source_batch(const SourceBatch<T>& b, hipStream_t st) {
+  if (b.total == 0) return hipSuccess;
+  hipLaunchKernelGGL(source_kernel_batch<T>, dim3(b.total), dim3(256), 0, st, b);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_record_batch(const RecordBatch<T>& b, hipStream_t st) {
+  if (b.total == 0) return hipSuccess;
+  hipLaunchKernelGGL(record_kernel_batch<T>, dim3((b.total + 255) / 256), dim3(256), 0, st, b);
   return hipGetLastError();
 }
 
@@ -1175,8 +1309,18 @@ hipError_t launch_energy(const EnergyArgs<T>& e, int nblocks, hipStream_t st) {
 
 template hipError_t launch_stage<float>(int, int, const StageArgs<float>&, hipStream_t);
 template hipError_t launch_stage<double>(int, int, const StageArgs<double>&, hipStream_t);
-template hipError_t launch_edge<float>(int, const StageArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_edge<double>(int, const StageArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_edge<float>(int, const StageArgs<float>&, hipStream_t);
+template hipError_t launch_edge<double>(int, const StageArgs<double>&, hipStream_t);
+template int edge_blocks<float>(const StageArgs<float>&);
+template int edge_blocks<double>(const StageArgs<double>&);
+template hipError_t launch_stage_batch<float>(int, int, const BatchArgs<float>&, bool, hipStream_t);
+template hipError_t launch_stage_batch<double>(int, int, const BatchArgs<double>&, bool, hipStream_t);
+template hipError_t launch_edge_batch<float>(int, const BatchArgs<float>&, hipStream_t);
+template hipError_t launch_edge_batch<double>(int, const BatchArgs<double>&, hipStream_t);
+template hipError_t launch_source_batch<float>(const SourceBatch<float>&, hipStream_t);
+template hipError_t launch_source_batch<double>(const SourceBatch<double>&, hipStream_t);
+template hipError_t launch_record_batch<float>(const RecordBatch<float>&, hipStream_t);
+template hipError_t launch_record_batch<double>(const RecordBatch<double>&, hipStream_t);
 template hipError_t launch_source<float>(const SourceArgs<float>&, int, hipStream_t);
 template hipError_t launch_source<double>(const SourceArgs<double>&, int, hipStream_t);
 template hipError_t launch_record<float>(const float*, std::size_t, const long long*, int, float*, hipStream_t);

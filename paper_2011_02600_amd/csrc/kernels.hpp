@@ -25,6 +25,7 @@ struct StageArgs {
   int nxt, nyt, nzc, ntiles;
   int ncol;
   int read_dq;
+  int ex, ey;         // edge kernel: last q column / last r row
   int traction[6];
   T Ak, Bk, dt;
   T inv_h[3];
@@ -62,10 +63,51 @@ struct EnergyArgs {
   double w[kMaxM];
 };
 
+// several grids in one launch: args[g] for grid g, whose blocks are
+// first[g] .. first[g+1]-1 of the launch (first[0] = 0, total blocks)
+template <typename T>
+struct BatchArgs {
+  const StageArgs<T>* args;
+  const int* first;
+  int n, total;
+};
+
+template <typename T>
+struct RecordArgs {
+  const T* q;
+  std::size_t field;
+  const long long* off;
+  T* out;  // this step's slot
+};
+
+template <typename T>
+struct SourceBatch {
+  const SourceArgs<T>* args;
+  const int* first;
+  int n, total;
+};
+
+template <typename T>
+struct RecordBatch {
+  const RecordArgs<T>* args;
+  const int* first;
+  int n, total;
+};
+
 template <typename T>
 hipError_t launch_stage(int order, int ty, const StageArgs<T>& a, hipStream_t st);
 template <typename T>
-hipError_t launch_edge(int order, const StageArgs<T>& a, int ex, int ey, hipStream_t st);
+hipError_t launch_edge(int order, const StageArgs<T>& a, hipStream_t st);
+template <typename T>
+hipError_t launch_stage_batch(int order, int ty, const BatchArgs<T>& b, bool buf, hipStream_t st);
+template <typename T>
+int edge_blocks(const StageArgs<T>& a);
+template <typename T>
+hipError_t launch_edge_batch(int order, const BatchArgs<T>& b, hipStream_t st);
+template <typename T>
+hipError_t launch_source_batch(const SourceBatch<T>& b, hipStream_t st);
+template <typename T>
+hipError_t launch_record_batch(const RecordBatch<T>& b, hipStream_t st);
 template <typename T>
 hipError_t launch_source(const SourceArgs<T>& s, int nsrc, hipStream_t st);
 template <typename T>

@@ -54,6 +54,7 @@ def lib():
             "sbp_set_launch": [c_void_p, c_int, c_int],
             "sbp_time": [c_void_p, P(c_double), P(ctypes.c_longlong)],
             "sbp_set_profiling": [c_void_p, c_int],
+            "sbp_step_batch": [c_void_p, c_int, c_int, P(c_double)],
             "sbp_profile": [c_void_p, P(c_double), P(c_double), P(ctypes.c_longlong), P(ctypes.c_longlong)],
             "sbp_destroy": [c_void_p],
         }
@@ -148,6 +149,15 @@ def sbp_energy(h):
 
 def sbp_set_launch(h, ty, zchunk):
     _check(lib().sbp_set_launch(h, int(ty), int(zchunk)))
+
+
+def sbp_step_batch(handles, nsteps, dts):
+    """Advance several handles (same dtype and stream) by nsteps steps of
+    their own dt in shared launches; synchronises the stream."""
+    n = len(handles)
+    arr = (ctypes.c_void_p * n)(*handles)
+    d = (ctypes.c_double * n)(*[float(x) for x in dts])
+    _check(lib().sbp_step_batch(arr, n, int(nsteps), d))
 
 
 def sbp_set_profiling(h, on):

@@ -294,3 +294,111 @@ def test_error_paths_on_device():
     with pytest.raises(sbp.SBPError) as e:
         sbp.Solver(bad, order=4, dtype="f32", gamma=[0] * 6)
     assert e.value.code == sbp.SBP_EINVAL
+
+
+def test_profiling_changes_nothing():
+    """sbp_set_profiling only times launches: the state after stepping with
+    it on is bitwise the state without it, and the reported node count is
+    the tiled part of the grid (all but the last q column, and the last r
+    row when nr - 1 is a multiple of the tile height)."""
+    say("case: profiling on/off, order 6 f32 65x41x29")
+    nq, nr, ns = 65, 41, 29
+    xyz = W.warped_mesh(nq, nr, ns, seed=9)
+    med = W.random_medium((ns, nr, nq), 2)
+    Q = W.random_state((ns, nr, nq), 4, smooth=True)
+    outs = []
+    for prof in (False, True):
+        s = make_solver(xyz, 6, "f32", [1, 0, 0, 0, 0, 1], medium=med)
+        s.set_state(Q)
+        s.set_profiling(prof)
+        s.step(3, 1e-3)
+        outs.append(s.get_state().cpu().numpy())
+        stage_ms, edge_ms, n, nodes = s.profile()
+        if prof:
+            assert n == 15 and stage_ms > 0 and edge_ms > 0
+            assert nodes == (nq - 1) * (nr - 1) * ns
+        else:
+            assert n == 0
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+BATCH_SHOTS = [
+    # order, (nq, nr, ns), source, receivers
+    (4, (33, 25, 21), True, True),
+    (6, (49, 41, 37), True, False),
+    (6, (29, 33, 24), False, True),
+    (2, (40, 17, 30), False, False),
+    (4, (65, 41, 19), True, True),
+]
+
+
+def _batch_solvers(dtype, io=True):
+    out = []
+    for n, (order, (nq, nr, ns), src, rec) in enumerate(BATCH_SHOTS):
+        xyz = W.warped_mesh(nq, nr, ns, seed=30 + n)
+        med = W.random_medium((ns, nr, nq), 40 + n)
+        s = make_solver(xyz, order, dtype, [1, 0, 0.5, 0, -1, 0], medium=med)
+        s.set_state(W.random_state((ns, nr, nq), 50 + n, smooth=True))
+        if src and io:
+            s.add_source((0.31 + 0.05 * n, 0.5, 0.47), (0.2, 0.1, -0.3, 1.0, 0.0, 0.4), 0, 8.0, 0.05)
+        if rec and io:
+            s.record(np.array([[1, 2, 3], [nq - 1, nr // 2, ns - 1], [nq // 2, 0, 0]]), 64)
+        out.append(s)
+    return out
+
+
+@pytest.mark.parametrize("io", [False, True])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_equals_separate_steps(dtype, io):
+    """sbp_step_batch over grids of uneven size and orders 2, 4, 6 (three
+    launch groups), with (io) or without sources and receivers, for 40 steps
+    (two chunks of per-step tables): states, times and receiver traces equal
+    those of stepping every handle alone.  The batched launches run the same
+    kernel bodies as sbp_step (instantiated with their arguments read from a
+    device table instead of passed by value), so the results agree to
+    rounding: relative max difference below 1e-5 (f32) / 1e-12 (f64)."""
+    say("case: batch of %d shots %s io=%s, 40 steps" % (len(BATCH_SHOTS), dtype, io))
+    sbp = sbp_mod()
+    tol = 1e-5 if dtype == "f32" else 1e-12
+    dts = [1.0e-3 * (1 + 0.1 * n) for n in range(len(BATCH_SHOTS))]
+    alone = _batch_solvers(dtype, io)
+    for s, d in zip(alone, dts):
+        s.step(40, d)
+    together = _batch_solvers(dtype, io)
+    sbp.sbp_step_batch([s.h for s in together], 40, dts)
+    report = []
+    for n, (a, b) in enumerate(zip(alone, together)):
+        x = a.get_state().cpu().numpy().astype(np.float64)
+        y = b.get_state().cpu().numpy().astype(np.float64)
+        es = rel_max(y, x)
+        assert a.time() == b.time(), n
+        et = 0.0
+        if BATCH_SHOTS[n][3] and io:
+            ta = a.traces.cpu().numpy().astype(np.float64)
+            tb = b.traces.cpu().numpy().astype(np.float64)
+            et = rel_max(tb, ta)
+            if et > tol:
+                rows = [int(r) for r in np.nonzero(np.abs(ta - tb).reshape(ta.shape[0], -1).max(axis=1))[0]]
+                say("  shot %d traces differ at steps %s" % (n, rows[:12]))
+        report.append((n, es, et))
+    say("  (shot, state rel max, traces rel max): %s" % ["(%d, %.2e, %.2e)" % r for r in report])
+    for n, es, et in report:
+        assert es <= tol and et <= tol, n
+    for s in alone + together:
+        s.close()
+
+
+def test_batch_error_paths():
+    say("case: batch error paths")
+    sbp = sbp_mod()
+    a = _batch_solvers("f32")[:2]
+    b = _batch_solvers("f64")[:1]
+    with pytest.raises(RuntimeError):
+        sbp.sbp_step_batch([a[0].h, b[0].h], 1, [1e-3, 1e-3])      # mixed dtype
+    with pytest.raises(RuntimeError):
+        sbp.sbp_step_batch([a[0].h, a[0].h], 1, [1e-3, 1e-3])      # same handle twice
+    with pytest.raises(RuntimeError):
+        sbp.sbp_step_batch([a[0].h, a[1].h], 1, [1e-3, -1.0])      # bad dt
+    for s in a + b:
+        s.close()

@@ -17,6 +17,10 @@ not available):
   (each at most 5 % of the depth), transfinite mesh, a 1 km low-velocity
   layer over a half-space (LOH1-like, Sec. 7.1), a point moment-tensor
   source with a Ricker wavelet and 64 surface receivers.
+* ``batched_shots``  32 independent cubes of uneven size (65^3 .. 193^3),
+  orders 4 and 6 alternating, FP32, each over its own Gaussian-random-field
+  medium (correlation length 10 cells, at most +-10 % around the half-space
+  values), a Ricker moment source and 16 surface receivers.
 
 Array convention: grid functions have shape (ns, nr, nq), q fastest; node
 coordinates are returned as xyz with shape (3, ns, nr, nq).
@@ -185,3 +189,47 @@ def warped_mesh(nq, nr, ns, seed, amp=0.04):
         out[c] = X[c] + a * np.sin(2 * np.pi * q + ph[0]) * np.sin(2 * np.pi * r + ph[1]) \
             * np.sin(2 * np.pi * s + ph[2])
     return out
+
+
+def grf(shape, corr_cells, seed, amp=0.1):
+    """Gaussian random field: white noise filtered in Fourier space by
+    exp(-|k|^2 l^2 / 2), l = corr_cells grid spacings, scaled so that its
+    largest magnitude is `amp`."""
+    rng = np.random.default_rng(seed)
+    w = rng.standard_normal(shape)
+    k = np.meshgrid(*[2 * np.pi * np.fft.fftfreq(n) for n in shape], indexing="ij", sparse=True)
+    k2 = sum(kk ** 2 for kk in k)
+    f = np.fft.ifftn(np.fft.fftn(w) * np.exp(-0.5 * k2 * corr_cells ** 2)).real
+    return amp * f / np.abs(f).max()
+
+
+def batched_shots(nshots=32, seed=0, h=0.05, cfl=0.5, corr_cells=10, amp=0.1, f0=4.0, nrec_side=4):
+    """Independent shots for batched stepping: cube i has n_i points per axis,
+    n_i drawn from {65, 69, ..., 193} with `seed`, interior order 4 for even i
+    and 6 for odd i, spacing h (km).  Medium: the half-space values
+    (cs 3.464, cp 6.0, rho 2.7) times 1 + delta, one random field (grf) for
+    cp and cs together (their ratio stays fixed) and one for rho.  Free
+    surface on top, absorbing elsewhere; a Ricker moment source (M = sxy,
+    f0, t0 = 1.2 / f0) at a seeded point of the central region; nrec_side^2
+    receivers on the top face."""
+    rng = np.random.default_rng(seed)
+    sizes = 65 + 4 * rng.integers(0, 33, size=nshots)
+    shots = []
+    for i, n in enumerate(sizes):
+        n = int(n)
+        xyz = unit_cube(n, n, n) * (h * (n - 1))
+        shape = (n, n, n)
+        dv = grf(shape, corr_cells, 1000 * seed + 2 * i, amp)
+        dr = grf(shape, corr_cells, 1000 * seed + 2 * i + 1, amp)
+        cs = 3.464 * (1 + dv)
+        cp = 6.0 * (1 + dv)
+        rho = 2.7 * (1 + dr)
+        src = tuple(rng.uniform(0.35, 0.65, size=3))
+        step = (n - 1) / nrec_side
+        rec = [(int(round(step * (a + 0.5))), int(round(step * (b + 0.5))), n - 1)
+               for b in range(nrec_side) for a in range(nrec_side)]
+        shots.append(dict(xyz=xyz, rho=rho, cp=cp, cs=cs, order=4 if i % 2 == 0 else 6,
+                          gamma=(0.0, 0.0, 0.0, 0.0, 0.0, 1.0), dt=cfl_dt(xyz, cp, cfl),
+                          src_xi=src, src_M=(0.0, 0.0, 0.0, 1.0, 0.0, 0.0), src_f0=f0, src_t0=1.2 / f0,
+                          receivers=np.array(rec, dtype=np.int32)))
+    return shots
