@@ -103,13 +103,17 @@ def run_batched(args, W, sbp, torch, np, dev):
     print("bench: generating 32 shots", file=sys.stderr, flush=True)
     shots = W.batched_shots(32)
     solvers = []
+    shapes = []
     for n, sh in enumerate(shots):
         s = sbp.Solver(sh["xyz"], order=sh["order"], dtype="f32", gamma=sh["gamma"], device=dev)
         s.set_material(sh["rho"], sh["cp"], sh["cs"])
         s.add_source(sh["src_xi"], sh["src_M"], sbp.SBP_STF_RICKER, sh["src_f0"], sh["src_t0"])
         s.record(sh["receivers"], 2 * (warm + steps))
+        ty, zc, _ = s.autotune(3)
+        shapes.append((ty, zc))
         solvers.append(s)
-        print("bench: shot %d: %d^3 order %d" % (n, sh["xyz"].shape[1], sh["order"]), file=sys.stderr, flush=True)
+        print("bench: shot %d: %d^3 order %d, launch ty %d zchunk %d" % (n, sh["xyz"].shape[1], sh["order"], ty, zc),
+              file=sys.stderr, flush=True)
     hs = [s.h for s in solvers]
     dts = [sh["dt"] for sh in shots]
     stream = solvers[0].stream
@@ -155,7 +159,8 @@ def run_batched(args, W, sbp, torch, np, dev):
                                "alternating, Gaussian-random-field media (10-cell correlation, +-10 %), "
                                "Ricker moment source, 16 surface receivers each, CFL 0.5",
                    "sizes": [int(sh["xyz"].shape[1]) for sh in shots],
-                   "orders": [sh["order"] for sh in shots], "points": points},
+                   "orders": [sh["order"] for sh in shots], "points": points,
+                   "launch": [{"ty": t, "zchunk": z} for t, z in shapes]},
         "mpts_stage_per_s": round(points * 5 * steps / secs / 1e6, 1),
         "one_by_one": {"ms": round(seq_ms, 2), "shots_per_s": round(len(shots) / (seq_ms / 1e3), 3),
                        "batch_speedup": round(seq_ms / batch_ms, 3)},

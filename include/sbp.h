@@ -169,11 +169,15 @@ int sbp_step(sbp_handle h, int nsteps, double dt);
  * stage one stage-kernel and one edge-kernel launch for all handles of the
  * same order and tile height, one launch for all their point sources, and
  * one receiver launch per step.  Each handle's state, time, step count and
- * receiver traces end up bitwise as after sbp_step(hs[i], nsteps, dt[i]).
+ * receiver traces end up as after sbp_step(hs[i], nsteps, dt[i]).
  * All handles need the same dtype and the same stream, distinct handles and
- * a medium; the argument tables live in hs[0]'s workspace.  Synchronises the
- * stream before returning.  Batched stepping of many independent sources or
- * media ("shots") on grids of uneven size.
+ * a medium; the argument tables live in hs[0]'s workspace.  Each handle's
+ * tile height is kept; the s-chunk length is chosen for the batch as a whole
+ * (the handles' own settings are restored on return).  Synchronises the
+ * stream before returning.  Results agree with separate sbp_step calls to
+ * rounding (the batched kernels are separate instantiations of the same
+ * kernel bodies).  Batched stepping of many independent sources or media
+ * ("shots") on grids of uneven size.
  */
 int sbp_step_batch(sbp_handle* hs, int n, int nsteps, const double* dt);
 
@@ -214,6 +218,17 @@ int sbp_set_launch(sbp_handle h, int ty, int zchunk);
 int sbp_set_profiling(sbp_handle h, int on);
 int sbp_profile(sbp_handle h, double* stage_ms, double* edge_ms, long long* nstages,
                 long long* stage_nodes);
+
+/*
+ * Launch-shape autotuner.  Times `reps` right-hand-side evaluations of the
+ * handle's own grid for each candidate launch shape (tile height 8, and 16
+ * for SBP_F32 at orders up to 6; the cost model's number of s-chunks and one
+ * fewer / one more) and keeps the fastest, as sbp_set_launch would.  Writes
+ * the chosen tile height, s-chunk length and its time per evaluation (ms) to
+ * the outputs (each may be NULL).  The state and time are not changed; call
+ * it between steps.  Synchronises the stream.
+ */
+int sbp_autotune(sbp_handle h, int reps, int* ty, int* zchunk, double* ms);
 
 /* Current time and number of completed steps. */
 int sbp_time(sbp_handle h, double* t, long long* steps);

@@ -599,10 +599,59 @@ int do_steps_batch(sbp_ctx** hs, int n, int nsteps, const double* dt) {
   hipStream_t st = h0->stream;
   const BatchRegion R = batch_region();
   char* base = h0->ws + h0->off_batch;
+  // s-chunks for the batch: every grid's own automatic choice assumes it has
+  // the whole GPU; here one chunk length L serves all grids (whatever their
+  // own setting), picked by the same wave cost model over the total work,
+  // waves x (L + warm-up)
+  std::vector<int> zsave(n);
   for (int g = 0; g < n; ++g) {
-    int rc = prepare_bounds(hs[g]);
+    zsave[g] = hs[g]->zchunk;
+    int rc = prepare_bounds(hs[g]);  // tiles across s (nxt, nyt)
     if (rc) return rc;
   }
+  {
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      int v = 0;
+      if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+    }
+    int nsmax = 0;
+    for (int g = 0; g < n; ++g) nsmax = std::max(nsmax, hs[g]->g.ns);
+    long long best = -1;
+    int bestL = nsmax;
+    for (int L = nsmax; L >= 8; L = L * 3 / 4) {
+      long long tiles = 0, planes = 0;
+      for (int g = 0; g < n; ++g) {
+        const sbp_ctx* h = hs[g];
+        const int Lg = std::min(L, h->g.ns);
+        const int nz = (h->g.ns + Lg - 1) / Lg;
+        tiles += (long long)h->nxt * h->nyt * nz;
+        planes = std::max<long long>(planes, (h->g.ns + nz - 1) / nz + h->cl.r + h->cl.q + 1);
+      }
+      const long long cost = (tiles + cus - 1) / cus * planes;
+      if (best < 0 || cost < best) {
+        best = cost;
+        bestL = L;
+      }
+    }
+    for (int g = 0; g < n; ++g) {
+      hs[g]->zchunk = std::min(bestL, hs[g]->g.ns);
+      hs[g]->bounds_dirty = true;
+      int rc = prepare_bounds(hs[g]);
+      if (rc) return rc;
+    }
+  }
+  // the handles' own launch settings are restored when the call returns
+  struct Restore {
+    sbp_ctx** hs;
+    const std::vector<int>& z;
+    ~Restore() {
+      for (std::size_t g = 0; g < z.size(); ++g) {
+        hs[g]->zchunk = z[g];
+        hs[g]->bounds_dirty = true;
+      }
+    }
+  } restore{hs, zsave};
   // groups: handles sorted by (order, tile height)
   std::vector<int> ord(n);
   for (int g = 0; g < n; ++g) ord[g] = g;
@@ -798,6 +847,77 @@ int do_energy(sbp_ctx* h, double* E) {
 }  // namespace
 
 // ============================================================================
+namespace {
+
+// Launch-shape autotuner: times `reps` right-hand-side evaluations (stage and
+// edge kernel, sources off) for each candidate tile height and number of
+// s-chunks and keeps the fastest.  A right-hand-side evaluation writes only
+// the Runge-Kutta register and the second state buffer, which hold nothing
+// between steps, so the state is untouched.
+template <typename T>
+int do_autotune(sbp_ctx* h, int reps, int* best_ty, int* best_zchunk, double* best_ms) {
+  std::vector<int> tys{8};
+  if (sizeof(T) == 4) tys.push_back(16);
+  const std::vector<Src> saved = h->src;
+  h->src.clear();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double best = -1.0;
+  int bty = h->ty, bzc = h->zchunk;
+  int rc = SBP_OK;
+  for (int ty : tys) {
+    if (ty < h->cl.m) continue;
+    // the cost model's chunk count, and one fewer / more chunks
+    h->ty = ty;
+    h->zchunk = 0;
+    h->bounds_dirty = true;
+    if ((rc = prepare_bounds(h))) break;
+    const int nz0 = h->nzc;
+    for (int nz = std::max(1, nz0 - 1); nz <= nz0 + 1 && rc == SBP_OK; ++nz) {
+      h->ty = ty;
+      h->zchunk = (h->g.ns + nz - 1) / nz;
+      h->bounds_dirty = true;
+      if ((rc = prepare_bounds(h))) break;
+      StageArgs<T> a = stage_args<T>(h);
+      T* qa = (T*)(h->ws + h->off_qa);
+      T* qb = (T*)(h->ws + h->off_qb);
+      T* qin = h->cur ? qb : qa;
+      T* qout = h->cur ? qa : qb;
+      if ((rc = run_stage<T>(h, a, 0, 1.0, h->t, true, qin, qout))) break;  // warm-up
+      if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = fail(SBP_EHIP, "hipEventRecord failed"); break; }
+      for (int r = 0; r < reps && rc == SBP_OK; ++r) rc = run_stage<T>(h, a, 0, 1.0, h->t, true, qin, qout);
+      if (rc) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = fail(SBP_EHIP, "event timing failed");
+        break;
+      }
+      const double per = ms / reps;
+      if (best < 0 || per < best) {
+        best = per;
+        bty = ty;
+        bzc = h->zchunk;
+      }
+    }
+    if (rc) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->src = saved;
+  h->ty = bty;
+  h->zchunk = bzc;
+  h->bounds_dirty = true;
+  if (rc) return rc;
+  if (best_ty) *best_ty = bty;
+  if (best_zchunk) *best_zchunk = bzc;
+  if (best_ms) *best_ms = best;
+  return SBP_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* sbp_last_error(void) { return g_err.c_str(); }
@@ -1102,6 +1222,14 @@ int sbp_set_launch(sbp_handle h, int ty, int zchunk) {
   h->zchunk = zchunk;
   h->bounds_dirty = true;
   return SBP_OK;
+}
+
+int sbp_autotune(sbp_handle h, int reps, int* ty, int* zchunk, double* ms) {
+  if (!h) return fail(SBP_EINVAL, "NULL handle");
+  if (!h->have_material) return fail(SBP_ESTATE, "sbp_set_material has not been called");
+  if (reps < 1) return fail(SBP_EINVAL, "reps must be >= 1");
+  return h->dtype == SBP_F32 ? do_autotune<float>(h, reps, ty, zchunk, ms)
+                             : do_autotune<double>(h, reps, ty, zchunk, ms);
 }
 
 int sbp_time(sbp_handle h, double* t, long long* steps) {

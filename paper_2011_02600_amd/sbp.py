@@ -55,6 +55,7 @@ def lib():
             "sbp_time": [c_void_p, P(c_double), P(ctypes.c_longlong)],
             "sbp_set_profiling": [c_void_p, c_int],
             "sbp_step_batch": [c_void_p, c_int, c_int, P(c_double)],
+            "sbp_autotune": [c_void_p, c_int, P(c_int), P(c_int), P(c_double)],
             "sbp_profile": [c_void_p, P(c_double), P(c_double), P(ctypes.c_longlong), P(ctypes.c_longlong)],
             "sbp_destroy": [c_void_p],
         }
@@ -158,6 +159,14 @@ def sbp_step_batch(handles, nsteps, dts):
     arr = (ctypes.c_void_p * n)(*handles)
     d = (ctypes.c_double * n)(*[float(x) for x in dts])
     _check(lib().sbp_step_batch(arr, n, int(nsteps), d))
+
+
+def sbp_autotune(h, reps=5):
+    """Time the candidate launch shapes and keep the fastest; returns
+    (ty, zchunk, ms per right-hand-side evaluation)."""
+    ty, zc, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(lib().sbp_autotune(h, int(reps), ctypes.byref(ty), ctypes.byref(zc), ctypes.byref(ms)))
+    return ty.value, zc.value, ms.value
 
 
 def sbp_set_profiling(h, on):
@@ -266,6 +275,9 @@ class Solver:
 
     def set_launch(self, ty=8, zchunk=0):
         sbp_set_launch(self.h, ty, zchunk)
+
+    def autotune(self, reps=5):
+        return sbp_autotune(self.h, reps)
 
     def set_profiling(self, on=True):
         sbp_set_profiling(self.h, on)

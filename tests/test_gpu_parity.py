@@ -402,3 +402,29 @@ def test_batch_error_paths():
         sbp.sbp_step_batch([a[0].h, a[1].h], 1, [1e-3, -1.0])      # bad dt
     for s in a + b:
         s.close()
+
+
+def test_autotune_keeps_state_and_picks_a_candidate():
+    """sbp_autotune times launch shapes with right-hand-side evaluations: the
+    state is unchanged, the chosen shape is one of the candidates, and
+    stepping with it agrees with the default shape to rounding."""
+    say("case: autotune order 4 f32 65x41x29")
+    nq, nr, ns = 65, 41, 29
+    xyz = W.warped_mesh(nq, nr, ns, seed=11)
+    med = W.random_medium((ns, nr, nq), 3)
+    Q = W.random_state((ns, nr, nq), 7, smooth=True)
+    ref = make_solver(xyz, 4, "f32", [1, 0, 0, 0, 0, 1], medium=med)
+    ref.set_state(Q)
+    ref.step(5, 1e-3)
+    want = ref.get_state().cpu().numpy().astype(np.float64)
+    ref.close()
+    s = make_solver(xyz, 4, "f32", [1, 0, 0, 0, 0, 1], medium=med)
+    s.set_state(Q)
+    ty, zc, ms = s.autotune(3)
+    say("  chosen ty %d zchunk %d, %.4f ms per evaluation" % (ty, zc, ms))
+    assert ty in (8, 16) and zc >= 1 and ms > 0
+    assert np.array_equal(s.get_state().cpu().numpy(), Q.astype(np.float32))
+    s.step(5, 1e-3)
+    got = s.get_state().cpu().numpy().astype(np.float64)
+    s.close()
+    assert rel_max(got, want) < 1e-5
