@@ -7,7 +7,8 @@ What the paper fixes (Sec. 4.1):
   * the upwind property: H (D+ - D-) symmetric negative semi-definite
     (Definition following eq. upw_SBP);
   * accuracy D x^k = k x^{k-1} (eq. acc): order 2p in the interior and p at
-    the boundary closures for interior order 2p;
+    the boundary closures for interior order 2p (interior order 2p + 1: p at
+    the boundary);
   * the interior forward stencil alpha_j (Table tab:upwind) and the backward
     one beta_j = -alpha_{-j} (Sec. 6.2).
 
@@ -23,11 +24,16 @@ constructs its own closures:
   free m x m block at the left end (and its antipersymmetric image at the
   right end), H = h diag(w_0..w_{m-1}, 1, ..., 1, w_{m-1}..w_0).
 
-The accuracy conditions on the first m rows are linear in (w, free block of
-A); they are solved exactly.  For orders 2 and 4 the solution is unique; for
-order 6 one entry, A[4][5], stays free and is fixed at 101/125, the value
-that minimises the spectral radius of the one-dimensional elastic operator
-with characteristic boundary penalties (a reading; the paper is silent).
+The accuracy conditions on the first m = order rows are linear in (w, free
+block of A); they are solved exactly.  For orders 2 and 4 the solution is
+unique.  For orders 3, 5 and 6 entries of the free block stay free (one,
+two, one) and are fixed (FREE_ENTRIES) at values where the one-dimensional
+elastic operator with characteristic boundary penalties has the smallest
+spectral radius — no larger than the interior stencil's max |alpha^| — with
+positive norm weights, taking the simplest rational among equivalent values:
+order 3 A[1][2] = 1/2 (w = 7/12, 3/4, 7/6), order 5 A[2][4] = 1/4,
+A[3][4] = 1/2 (w = 323/720, 203/240, 71/48, 451/720, 11/10), order 6
+A[4][5] = 101/125 (a reading; the paper is silent).
 S annihilates polynomials of degree < P, so D+ and D- share the accuracy of
 A + B/2.  The SBP identity and the semi-definiteness then hold by
 construction and are pinned separately by the tests.
@@ -56,10 +62,15 @@ UPWIND_ALPHA = {
 }
 
 # Orders whose boundary closures this oracle constructs.
-CLOSED_ORDERS = (2, 4, 6)
+CLOSED_ORDERS = (2, 3, 4, 5, 6)
 
-# Free closure entry for order 6 (see module docstring).
+# Free closure entries (see module docstring).
 ORDER6_FREE_A45 = Fr(101, 125)
+FREE_ENTRIES = {
+    3: {(1, 2): Fr(1, 2)},
+    5: {(2, 4): Fr(1, 4), (3, 4): Fr(1, 2)},
+    6: {(4, 5): ORDER6_FREE_A45},
+}
 
 
 def alpha_dict(order):
@@ -173,11 +184,11 @@ def closure(order):
                 row[i] -= k * xkm1
             rows.append(row)
             rhs.append(b)
-    if order == 6:
+    for pr, val in FREE_ENTRIES.get(order, {}).items():
         row = [Fr(0)] * nunk
-        row[uidx[(4, 5)]] = Fr(1)
+        row[uidx[pr]] = Fr(1)
         rows.append(row)
-        rhs.append(ORDER6_FREE_A45)
+        rhs.append(val)
     x = _solve_exact(rows, rhs, nunk)
     w = x[:m]
     Ablk = [[Fr(0)] * m for _ in range(m)]

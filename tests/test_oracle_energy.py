@@ -119,7 +119,7 @@ def sat_dissipation(blk, Q, gamma):
     return tot
 
 
-@pytest.mark.parametrize("order", [2, 4, 6])
+@pytest.mark.parametrize("order", [2, 3, 4, 5, 6])
 def test_volume_terms_give_surface_term(order):
     blk = make_block(order, seed=order)
     Q = W.random_state(blk.shape, 10 + order)
@@ -145,7 +145,7 @@ def test_negative_control_same_operator_breaks_identity():
     assert abs(got - want) > 1e-3 * abs(want)
 
 
-@pytest.mark.parametrize("order", [2, 4, 6])
+@pytest.mark.parametrize("order", [2, 3, 4, 5, 6])
 @pytest.mark.parametrize("gseed", [0, 1])
 def test_characteristic_sat_energy_rate(order, gseed):
     blk = make_block(order, seed=20 + order)

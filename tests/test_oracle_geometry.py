@@ -20,7 +20,7 @@ def affine_mesh(shape, seed):
     return X, A
 
 
-@pytest.mark.parametrize("order", [2, 4, 6])
+@pytest.mark.parametrize("order", [2, 3, 4, 5, 6])
 def test_affine_map_metrics_exact(order):
     """For x = A xi + b: J = det A and M = J dxi/dx = J A^{-1} (Sec. 2.2)."""
     X, A = affine_mesh((13, 14, 12), order)
@@ -33,7 +33,7 @@ def test_affine_map_metrics_exact(order):
             assert np.allclose(blk.M[xi][c], J * Ainv[xi, c], rtol=0, atol=1e-11 * abs(J))
 
 
-@pytest.mark.parametrize("order", [2, 4, 6])
+@pytest.mark.parametrize("order", [2, 3, 4, 5, 6])
 def test_discrete_metric_identity(order):
     """sum_xi D-_xi M[xi][c] = 0 for the conservative cofactor metrics."""
     X = W.warped_mesh(14, 13, 15, seed=order)
@@ -86,7 +86,7 @@ def test_metrics_converge_to_analytic(order):
     assert rates[-1] > order // 2 - 0.3, rates
 
 
-@pytest.mark.parametrize("order", [2, 4, 6])
+@pytest.mark.parametrize("order", [2, 3, 4, 5, 6])
 def test_discrete_delta_moments(order):
     """sum_ijk H_ijk J_ijk delta_ijk f_ijk = f(x_s) for tensor polynomials of
     degree < 2(p+1) per reference axis, including near a boundary."""
