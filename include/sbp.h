@@ -90,7 +90,12 @@ int sbp_workspace_bytes(int nq, int nr, int ns, int order, int dtype, size_t* by
  *               precision (x_xi = D0 x with D0 = (D+ + D-)/2, J = det, and the
  *               conservative cofactor form of J dxi/dx); a non-positive
  *               Jacobian anywhere is SBP_EINVAL.
- *  order        interior order of accuracy of the upwind pair: 2, 4 or 6.
+ *  order        interior order of accuracy of the upwind pair, 2 to 6
+ *               (Table tab:upwind).  The boundary closures are accurate to
+ *               order order / 2 (rounded down); the paper does not print
+ *               them: the library constructs them from the SBP and upwind
+ *               properties of Sec. 4.1, the entries those leave free fixed
+ *               where the spectral radius is smallest.
  *  dtype        SBP_F32 or SBP_F64 (every device array and kernel uses it).
  *  gamma        host, 6 doubles, reflection coefficient of eq. BC_General2
  *               per face in the order (q=0, q=1, r=0, r=1, s=0, s=1); each

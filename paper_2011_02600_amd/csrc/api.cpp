@@ -53,7 +53,7 @@ constexpr int kMaxRec = 65536;
 // kBatchSteps steps at a time; handles are grouped by (order, tile height)
 constexpr int kMaxBatch = 64;
 constexpr int kBatchSteps = 32;
-constexpr int kMaxGroups = 6;
+constexpr int kMaxGroups = 10;  // five orders x two tile heights
 
 constexpr int kMaxPart = 1024;
 constexpr double kPi = 3.14159265358979323846;
@@ -117,7 +117,7 @@ struct sbp_ctx {
 namespace {
 
 int check_dims(int nq, int nr, int ns, int order, int dtype) {
-  if (order != 2 && order != 4 && order != 6) return fail(SBP_EINVAL, "order must be 2, 4 or 6 (got %d)", order);
+  if (order < 2 || order > 6) return fail(SBP_EINVAL, "order must be 2, 3, 4, 5 or 6 (got %d)", order);
   if (dtype != SBP_F32 && dtype != SBP_F64) return fail(SBP_EINVAL, "dtype must be SBP_F32 or SBP_F64");
   const int mn = 2 * order;
   if (nq < mn || nr < mn || ns < mn)
@@ -592,7 +592,8 @@ int do_steps(sbp_ctx* h, int nsteps, double dt) {
 
 // Several handles advanced together: the same kernels and per-grid
 // arguments as do_steps, but each launch covers the tiles of all grids of
-// one (order, tile height) group.  Results are bitwise those of do_steps.
+// one (order, tile height) group.  Results agree with do_steps to rounding
+// (the batched kernels are compiled separately).
 template <typename T>
 int do_steps_batch(sbp_ctx** hs, int n, int nsteps, const double* dt) {
   sbp_ctx* h0 = hs[0];

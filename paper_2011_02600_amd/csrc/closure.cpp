@@ -10,9 +10,14 @@
 //   outside a free m x m corner block, H = diag(w_0..w_{m-1}, 1, ...),
 // where the corner block and the weights solve the accuracy conditions of the
 // first m rows (a linear least-squares problem that is consistent and has a
-// unique solution for orders 2 and 4; order 6 leaves A[4][5] free, fixed to
-// 101/125, the spectral-radius minimiser).  The system is solved with
-// Householder QR in long double.
+// unique solution for orders 2 and 4).  Orders 3, 5 and 6 leave entries of the
+// corner block free; they are fixed where the one-dimensional elastic operator
+// with characteristic penalties has the smallest spectral radius (no larger
+// than the interior stencil's) with positive weights, at the simplest
+// rational of equal radius: order 3 A[1][2] = 1/2, order 5 A[2][4] = 1/4 and
+// A[3][4] = 1/2, order 6 A[4][5] = 101/125.  For interior order 2p + 1 the
+// boundary accuracy is p, as for 2p.  The system is solved with Householder
+// QR in long double.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -28,11 +33,24 @@ struct Row {
   int n;
 };
 
-// Table tab:upwind, orders 2, 4 and 6: alpha_{-r} .. alpha_{q}.
+// Table tab:upwind, orders 2 to 6: alpha_{-r} .. alpha_{q}.
 const Row kTable[] = {
     {2, 0, {-3, 2, -1}, {2, 1, 2}, 3},
+    {3, 1, {-1, -1, 1, -1}, {3, 2, 1, 6}, 4},
     {4, 1, {-1, -5, 3, -1, 1}, {4, 6, 2, 2, 12}, 5},
+    {5, 2, {1, -1, -1, 1, -1, 1}, {20, 2, 3, 1, 4, 30}, 6},
     {6, 2, {1, -2, -7, 4, -1, 2, -1}, {30, 5, 12, 3, 2, 15, 60}, 7},
+};
+
+// Corner-block entries A[i][j] = num/den left free by the accuracy conditions.
+struct FreeEntry {
+  int order, i, j, num, den;
+};
+const FreeEntry kFree[] = {
+    {3, 1, 2, 1, 2},
+    {5, 2, 4, 1, 4},
+    {5, 3, 4, 1, 2},
+    {6, 4, 5, 101, 125},
 };
 
 long double binom(int n, int k) {
@@ -85,7 +103,7 @@ bool build_closure(int order, Closure* out, const char** err) {
   for (const Row& t : kTable)
     if (t.order == order) row = &t;
   if (!row) {
-    *err = "unsupported order (2, 4 or 6)";
+    *err = "unsupported order (2 to 6)";
     return false;
   }
   const int r = row->r;
@@ -142,11 +160,12 @@ bool build_closure(int order, Closure* out, const char** err) {
       ++neq;
     }
   }
-  if (order == 6) {
+  for (const FreeEntry& f : kFree) {
+    if (f.order != order) continue;
     std::vector<long double> eq(nunk, 0);
-    eq[uidx(4, 5)] = 1;
+    eq[uidx(f.i, f.j)] = 1;
     M.insert(M.end(), eq.begin(), eq.end());
-    b.push_back(101.0L / 125.0L);
+    b.push_back((long double)f.num / f.den);
     ++neq;
   }
   std::vector<long double> x;

@@ -29,7 +29,7 @@ struct Closure {
   double alpha[10] = {};  // interior D+ stencil alpha_{-r..q} (Table tab:upwind)
 };
 
-// Builds the closure for order 2, 4 or 6; returns false on failure (message
+// Builds the closure for orders 2 to 6; returns false on failure (message
 // in *err).
 bool build_closure(int order, Closure* out, const char** err);
 

@@ -37,9 +37,19 @@ struct Stencil<2> {
   static constexpr double a[3] = {-3.0 / 2, 2.0, -1.0 / 2};
 };
 template <>
+struct Stencil<3> {
+  static constexpr int R = 1, Q = 2, M = 3;
+  static constexpr double a[4] = {-1.0 / 3, -1.0 / 2, 1.0, -1.0 / 6};
+};
+template <>
 struct Stencil<4> {
   static constexpr int R = 1, Q = 3, M = 4;
   static constexpr double a[5] = {-1.0 / 4, -5.0 / 6, 3.0 / 2, -1.0 / 2, 1.0 / 12};
+};
+template <>
+struct Stencil<5> {
+  static constexpr int R = 2, Q = 3, M = 5;
+  static constexpr double a[6] = {1.0 / 20, -1.0 / 2, -1.0 / 3, 1.0, -1.0 / 4, 1.0 / 30};
 };
 template <>
 struct Stencil<6> {
@@ -1197,11 +1207,15 @@ hipError_t launch_stage(int order, int ty, const StageArgs<T>& a, hipStream_t st
   // 16-row tiles only for 4-byte types (LDS capacity)
   if (ty == 16 && sizeof(T) == 4) {
     if (order == 2) return launch_stage_t<T, 2, 16>(a, st);
+    if (order == 3) return launch_stage_t<T, 3, 16>(a, st);
     if (order == 4) return launch_stage_t<T, 4, 16>(a, st);
+    if (order == 5) return launch_stage_t<T, 5, 16>(a, st);
     if (order == 6) return launch_stage_t<T, 6, 16>(a, st);
   } else {
     if (order == 2) return launch_stage_t<T, 2, 8>(a, st);
+    if (order == 3) return launch_stage_t<T, 3, 8>(a, st);
     if (order == 4) return launch_stage_t<T, 4, 8>(a, st);
+    if (order == 5) return launch_stage_t<T, 5, 8>(a, st);
     if (order == 6) return launch_stage_t<T, 6, 8>(a, st);
   }
   return hipErrorInvalidValue;
@@ -1221,8 +1235,12 @@ hipError_t launch_edge(int order, const StageArgs<T>& a, hipStream_t st) {
   if (nb == 0) return hipSuccess;
   if (order == 2)
     hipLaunchKernelGGL((edge_kernel<T, 2, KZ>), dim3(nb), dim3(64, KZ), 0, st, a);
+  else if (order == 3)
+    hipLaunchKernelGGL((edge_kernel<T, 3, KZ>), dim3(nb), dim3(64, KZ), 0, st, a);
   else if (order == 4)
     hipLaunchKernelGGL((edge_kernel<T, 4, KZ>), dim3(nb), dim3(64, KZ), 0, st, a);
+  else if (order == 5)
+    hipLaunchKernelGGL((edge_kernel<T, 5, KZ>), dim3(nb), dim3(64, KZ), 0, st, a);
   else if (order == 6)
     hipLaunchKernelGGL((edge_kernel<T, 6, KZ>), dim3(nb), dim3(64, KZ), 0, st, a);
   else
@@ -1249,11 +1267,15 @@ hipError_t launch_stage_batch(int order, int ty, const BatchArgs<T>& b, bool buf
   if (b.total == 0) return hipSuccess;
   if (ty == 16 && sizeof(T) == 4) {
     if (order == 2) return launch_stage_batch_t<T, 2, 16>(b, buf, st);
+    if (order == 3) return launch_stage_batch_t<T, 3, 16>(b, buf, st);
     if (order == 4) return launch_stage_batch_t<T, 4, 16>(b, buf, st);
+    if (order == 5) return launch_stage_batch_t<T, 5, 16>(b, buf, st);
     if (order == 6) return launch_stage_batch_t<T, 6, 16>(b, buf, st);
   } else {
     if (order == 2) return launch_stage_batch_t<T, 2, 8>(b, buf, st);
+    if (order == 3) return launch_stage_batch_t<T, 3, 8>(b, buf, st);
     if (order == 4) return launch_stage_batch_t<T, 4, 8>(b, buf, st);
+    if (order == 5) return launch_stage_batch_t<T, 5, 8>(b, buf, st);
     if (order == 6) return launch_stage_batch_t<T, 6, 8>(b, buf, st);
   }
   return hipErrorInvalidValue;
@@ -1265,8 +1287,12 @@ hipError_t launch_edge_batch(int order, const BatchArgs<T>& b, hipStream_t st) {
   if (b.total == 0) return hipSuccess;
   if (order == 2)
     hipLaunchKernelGGL((edge_kernel_batch<T, 2, KZ>), dim3(b.total), dim3(64, KZ), 0, st, b);
+  else if (order == 3)
+    hipLaunchKernelGGL((edge_kernel_batch<T, 3, KZ>), dim3(b.total), dim3(64, KZ), 0, st, b);
   else if (order == 4)
     hipLaunchKernelGGL((edge_kernel_batch<T, 4, KZ>), dim3(b.total), dim3(64, KZ), 0, st, b);
+  else if (order == 5)
+    hipLaunchKernelGGL((edge_kernel_batch<T, 5, KZ>), dim3(b.total), dim3(64, KZ), 0, st, b);
   else if (order == 6)
     hipLaunchKernelGGL((edge_kernel_batch<T, 6, KZ>), dim3(b.total), dim3(64, KZ), 0, st, b);
   else

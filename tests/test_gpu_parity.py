@@ -96,6 +96,16 @@ RHS_CASES = [
     (6, (15, 25, 97), "f64", 1),
     (2, (9, 17, 40), "f32", 0),
     (6, (14, 33, 129), "f32", 0),
+    # odd interior orders 3 and 5: minimum size, ragged multi-tile shapes,
+    # edge-kernel shapes
+    (3, (6, 6, 6), "f64", 0),
+    (5, (10, 10, 10), "f64", 1),
+    (3, (15, 19, 70), "f64", 1),
+    (3, (13, 17, 65), "f32", 0),
+    (5, (17, 13, 131), "f64", 0),
+    (5, (17, 13, 131), "f32", 1),
+    (5, (15, 25, 97), "f64", 0),
+    (3, (14, 33, 129), "f64", 1),
 ]
 
 
@@ -131,23 +141,24 @@ def test_rhs_parity(order, shape, dtype, variant):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("size", [(49, 45, 37), (65, 41, 33)])
-def test_topo_layer_small_100_steps(dtype, size):
+@pytest.mark.parametrize("order,size", [(6, (49, 45, 37)), (6, (65, 41, 33)), (3, (65, 41, 33)),
+                                        (5, (49, 45, 37))])
+def test_topo_layer_small_100_steps(dtype, order, size):
     """The curvilinear layered workload (topography, transfinite mesh, soft
     layer over a half-space, Ricker moment source, surface receivers) at a
     reduced size: 100 steps, state and receiver traces against the oracle.
-    The second size has its last q column and r row on the edge kernel, like
-    the full-size workload."""
+    The (65, 41, 33) size has its last q column and r row on the edge kernel,
+    like the full-size workload."""
     nq, nr, ns = size
-    say("case: topo_layer %dx%dx%d order 6 %s 100 steps" % (nq, nr, ns, dtype))
+    say("case: topo_layer %dx%dx%d order %d %s 100 steps" % (nq, nr, ns, order, dtype))
     wl = W.topo_layer(nq=nq, nr=nr, ns=ns, nrec_side=4)
-    s = make_solver(wl["xyz"], 6, dtype, wl["gamma"], medium=(wl["rho"], wl["cp"], wl["cs"]))
+    s = make_solver(wl["xyz"], order, dtype, wl["gamma"], medium=(wl["rho"], wl["cp"], wl["cs"]))
     s.add_source(wl["src_xi"], wl["src_M"], 0, wl["src_f0"], wl["src_t0"])
     traces = s.record(wl["receivers"], 100)
     s.step(100, wl["dt"])
     got = s.get_state().cpu().numpy().astype(np.float64)
     tr = traces.cpu().numpy().astype(np.float64)
-    blk = E.Block(wl["xyz"], 6).set_material(wl["rho"], wl["cp"], wl["cs"])
+    blk = E.Block(wl["xyz"], order).set_material(wl["rho"], wl["cp"], wl["cs"])
     src = E.Source(blk, wl["src_xi"], wl["src_M"], E.STF_RICKER, wl["src_f0"], wl["src_t0"])
     want, _, wtr = E.run(blk, wl["Q0"], 100, wl["dt"], wl["gamma"], sources=[src], receivers=wl["receivers"])
     err = rel_l2(got, want)
@@ -330,6 +341,8 @@ BATCH_SHOTS = [
     (6, (29, 33, 24), False, True),
     (2, (40, 17, 30), False, False),
     (4, (65, 41, 19), True, True),
+    (3, (37, 29, 22), True, True),
+    (5, (45, 26, 27), False, True),
 ]
 
 
@@ -351,7 +364,7 @@ def _batch_solvers(dtype, io=True):
 @pytest.mark.parametrize("io", [False, True])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_batch_equals_separate_steps(dtype, io):
-    """sbp_step_batch over grids of uneven size and orders 2, 4, 6 (three
+    """sbp_step_batch over grids of uneven size and orders 2 to 6 (five
     launch groups), with (io) or without sources and receivers, for 40 steps
     (two chunks of per-step tables): states, times and receiver traces equal
     those of stepping every handle alone.  The batched launches run the same

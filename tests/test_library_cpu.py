@@ -33,13 +33,13 @@ def test_workspace_size_and_validation():
     assert b >= 39 * n
     b32 = sbp.sbp_workspace_bytes(21, 21, 21, 4, sbp.SBP_F32)
     assert b32 < b
-    for args in [(7, 21, 21, 4, sbp.SBP_F64), (21, 21, 11, 6, sbp.SBP_F32), (21, 21, 21, 5, sbp.SBP_F32),
-                 (21, 21, 21, 4, 16)]:
+    for args in [(7, 21, 21, 4, sbp.SBP_F64), (21, 21, 11, 6, sbp.SBP_F32), (21, 21, 21, 7, sbp.SBP_F32),
+                 (21, 21, 21, 1, sbp.SBP_F32), (21, 21, 9, 5, sbp.SBP_F64), (21, 21, 21, 4, 16)]:
         with pytest.raises(sbp.SBPError) as e:
             sbp.sbp_workspace_bytes(*args)
         assert e.value.code == sbp.SBP_EINVAL
     # minimum sizes are accepted
-    for order in (2, 4, 6):
+    for order in (2, 3, 4, 5, 6):
         sbp.sbp_workspace_bytes(2 * order, 2 * order, 2 * order, order, sbp.SBP_F32)
 
 
@@ -65,5 +65,11 @@ def test_init_rejects_bad_arguments_before_device_use():
 def test_header_documents_every_entry_point():
     txt = open(os.path.join(ROOT, "include", "sbp.h")).read()
     for n in declared_functions():
-        i = txt.index(n + "(")
-        assert "/*" in txt[max(0, i - 1500):i], n
+        i = re.search(r"^[a-z].*\b%s\(" % n, txt, re.M).start()  # the declaration's line
+        # a comment ends right above it, or above the declarations grouped
+        # with it (lines directly before it that are code)
+        lines = txt[:i].rstrip().split("\n")
+        while lines and lines[-1].strip() and not lines[-1].rstrip().endswith("*/") \
+                and not lines[-1].lstrip().startswith(("*", "/*")):
+            lines.pop()
+        assert lines and lines[-1].rstrip().endswith("*/"), n
