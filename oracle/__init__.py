@@ -23,6 +23,11 @@ elastic        metric terms, material, semi-discrete RHS (eq.
 kron_form      the same semi-discrete operator assembled literally as sparse
                Kronecker products with the rotated (n, m, l) boundary frame;
                used only as a brute-force pin of ``elastic`` on tiny grids
+adjoint        discrete adjoint of the fully discrete scheme (explicit sparse
+               transpose of ``kron_form``'s operator, reverse Runge-Kutta
+               sweep) and the misfit gradient with respect to the nodal
+               rho, lambda, mu (complex-step derivatives of ``elastic.rhs``);
+               an extension, not in the paper
 
 Array convention: every grid function is a numpy array of shape (ns, nr, nq)
 (C order, q fastest), so the q-derivative acts on axis 2, r on axis 1 and s
