@@ -194,6 +194,51 @@ int sbp_step_batch(sbp_handle* hs, int n, int nsteps, const double* dt);
 int sbp_rhs(sbp_handle h, void* out_device, double t);
 
 /*
+ * Discrete adjoint and misfit gradient (an extension built on the scheme; the
+ * paper has no adjoint).  The differentiated map is the fully discrete
+ * scheme as sbp_step runs it (the semi-discrete operator L of eq.
+ * gen_hyp_transformed_discrete_SAT, point sources, the five-stage Runge-Kutta
+ * scheme of Sec. 7) followed by the receivers (v after every step).
+ *
+ * sbp_adjoint_bytes: bytes of the caller-owned adjoint workspace that
+ * sbp_gradient needs for nsteps steps with a checkpoint every `every` steps:
+ * ceil(nsteps / every) + every saved states plus about 100 grid functions
+ * (nsteps = 0: the size sbp_adjoint_rhs needs).  every is clamped to
+ * [1, nsteps].
+ */
+int sbp_adjoint_bytes(sbp_handle h, int nsteps, int every, size_t* bytes);
+
+/*
+ * out_device = L^T lam_device: the transpose of the semi-discrete operator
+ * (volume terms and boundary penalties; sources do not enter), both 9 dense
+ * grid functions in the handle dtype on the device.  adj_ws: device,
+ * 256-byte aligned, >= sbp_adjoint_bytes(h, 0, 1, .) bytes, caller-owned,
+ * its contents scratch.  Computed as -W L_v(W^{-1} lam) + Bd W^{-1} lam +
+ * P^T lam (W the energy weights, Bd the boundary terms of the summation by
+ * parts identity, P the face penalty blocks).  Asynchronous.
+ */
+int sbp_adjoint_rhs(sbp_handle h, const void* lam_device, void* out_device, void* adj_ws, size_t adj_bytes);
+
+/*
+ * Gradient of chi = sum_n sum_r m(trace(n, r)) for a caller-chosen misfit m
+ * whose derivative dm/dtrace the caller supplies as residual_device
+ * ([nsteps][nrec][3], handle dtype, device; the receivers are those of the
+ * last sbp_record call, which must have nrec >= 1; for chi = 1/2 |traces -
+ * data|^2 the residual is traces - data).  Starting from the current state
+ * at the current time, runs nsteps steps of size dt (sources included,
+ * receiver traces not recorded), keeping a checkpoint every `every` steps in
+ * adj_ws, then the reverse sweep: each block of steps is recomputed from
+ * its checkpoint, each step's stage inputs from its state.  Writes d chi /
+ * d (rho, lambda, mu) at every node to grad_device (3 dense grid functions:
+ * rho, then lambda, then mu, with the other two held fixed) and, if
+ * qbar_device is not NULL, d chi / d Q0 (9 dense grid functions).  The
+ * handle ends as after sbp_step(h, nsteps, dt).  Synchronises the stream.
+ * About five forward step costs per step.
+ */
+int sbp_gradient(sbp_handle h, int nsteps, double dt, const void* residual_device, int every, void* adj_ws,
+                 size_t adj_bytes, void* grad_device, void* qbar_device);
+
+/*
  * Discrete energy 1/2 <Q, P~^{-1} Q>_H = 1/2 sum H_ijk J (rho |v|^2 +
  * sigma^T C^{-1} sigma) of the current state (eq. physical_energy_discrete
  * with the curvilinear weight J), accumulated in double.  Synchronises the

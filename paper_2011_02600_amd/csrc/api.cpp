@@ -14,6 +14,7 @@
 
 #include "../../include/sbp.h"
 #include "internal.hpp"
+#include "adjoint.hpp"
 #include "kernels.hpp"
 
 using namespace sbp;
@@ -479,6 +480,7 @@ StageArgs<T> stage_args(sbp_ctx* h) {
   a.nm = h->nm;
   a.ex = h->ex;
   a.ey = h->ey;
+  a.sat = 1;
   a.plane = h->plane;
   a.field = h->field;
   a.px = h->px;
@@ -917,6 +919,225 @@ int do_autotune(sbp_ctx* h, int reps, int* best_ty, int* best_zchunk, double* be
   return SBP_OK;
 }
 
+// ---- discrete adjoint ---------------------------------------------------------
+// Layout of the caller's adjoint workspace (byte offsets): checkpoints of the
+// state every `every` steps, the states of one block of steps, the stage
+// inputs of one step, the forward Runge-Kutta register, the adjoint state and
+// register, W^{-1} dQb, a right-hand-side buffer, the unit-material
+// coefficients, J and the three gradient fields.
+struct AdjLayout {
+  std::size_t ck = 0, blk = 0, st = 0, dqs = 0, qb = 0, dqb = 0, y = 0, r = 0, cu = 0, jac = 0, grad = 0, total = 0;
+  int nck = 0, every = 0;
+};
+
+AdjLayout adj_layout(const sbp_ctx* h, int nsteps, int every) {
+  AdjLayout L;
+  const std::size_t F = h->field * h->esize;
+  L.every = nsteps > 0 ? std::max(1, std::min(every, nsteps)) : 0;
+  L.nck = nsteps > 0 ? (nsteps + L.every - 1) / L.every : 0;
+  std::size_t o = 0;
+  auto take = [&](std::size_t bytes) {
+    std::size_t at = o;
+    o = align256(o + bytes);
+    return at;
+  };
+  L.ck = take((std::size_t)L.nck * 9 * F);
+  L.blk = take((std::size_t)L.every * 9 * F);
+  L.st = take(5 * 9 * F);
+  L.dqs = take(9 * F);
+  L.qb = take(9 * F);
+  L.dqb = take(9 * F);
+  L.y = take(9 * F);
+  L.r = take(9 * F);
+  L.cu = take(kNumCoef * F);
+  L.jac = take(F);
+  L.grad = take(3 * F);
+  L.total = o;
+  return L;
+}
+
+// One Runge-Kutta stage (or right-hand side) with explicit buffers and
+// coefficient array; sat = false leaves the boundary penalties out.
+template <typename T>
+int stage_explicit(sbp_ctx* h, const StageArgs<T>& base, int k, double dt, double tstage, const T* qin, T* qout,
+                   T* dq, bool rhs_only, const T* coef, bool sat, bool sources) {
+  StageArgs<T> b = base;
+  b.qin = qin;
+  b.qout = qout;
+  b.dq = dq;
+  b.read_dq = (!rhs_only && k > 0) ? 1 : 0;
+  b.Ak = rhs_only ? T(0) : (T)kRkA[k];
+  b.Bk = rhs_only ? T(0) : (T)kRkB[k];
+  b.dt = rhs_only ? T(1) : (T)dt;
+  b.coef = coef;
+  b.sat = sat ? 1 : 0;
+  HIPCHK(launch_stage<T>(h->order, h->ty, b, h->stream));
+  if (h->ex || h->ey) HIPCHK(launch_edge<T>(h->order, b, h->stream));
+  if (sources && !h->src.empty()) {
+    SourceArgs<T> s = source_args<T>(h, k, dt, tstage, rhs_only, qout);
+    s.dq = dq;
+    HIPCHK(launch_source<T>(s, (int)h->src.size(), h->stream));
+  }
+  return SBP_OK;
+}
+
+// One step q0 -> q1 at time tn; the inputs of stages 1..4 land in S[0..3].
+template <typename T>
+int step_explicit(sbp_ctx* h, const StageArgs<T>& base, double tn, double dt, const T* q0, T* const S[4], T* q1,
+                  T* dq) {
+  const T* in = q0;
+  for (int k = 0; k < 5; ++k) {
+    T* out = k < 4 ? S[k] : q1;
+    int rc = stage_explicit<T>(h, base, k, dt, tn + kRkC[k] * dt, in, out, dq, false, base.coef, true, true);
+    if (rc) return rc;
+    in = out;
+  }
+  return SBP_OK;
+}
+
+template <typename T>
+AdjArgs<T> adj_args(sbp_ctx* h, char* adj, const AdjLayout& L) {
+  AdjArgs<T> a{};
+  const Geometry& g = h->g;
+  a.nm = h->nm;
+  a.field = h->field;
+  a.nq = g.nq;
+  a.nr = g.nr;
+  a.ns = g.ns;
+  a.m = h->cl.m;
+  for (int i = 0; i < kMaxM; ++i) a.w[i] = (T)h->cl.w[i];
+  a.h[0] = (T)(1.0 / (g.nq - 1));
+  a.h[1] = (T)(1.0 / (g.nr - 1));
+  a.h[2] = (T)(1.0 / (g.ns - 1));
+  a.coef = (const T*)(h->ws + h->off_coef);
+  a.face = (const T*)h->ws;
+  for (int f = 0; f < 6; ++f) {
+    a.face_off[f] = h->off_face[f] / sizeof(T);
+    a.face_n[f] = h->face_n[f];
+    a.gamma[f] = (T)h->gamma[f];
+    a.traction[f] = (h->sat_variant == SBP_SAT_TRACTION && h->gamma[f] == 1.0) ? 1 : 0;
+  }
+  a.qb = (T*)(adj + L.qb);
+  a.dqb = (T*)(adj + L.dqb);
+  a.y = (T*)(adj + L.y);
+  a.r = (const T*)(adj + L.r);
+  a.jac = (const T*)(adj + L.jac);
+  a.grad = (T*)(adj + L.grad);
+  return a;
+}
+
+int check_adj_ws(const void* adj, std::size_t bytes, std::size_t need) {
+  if (!adj) return fail(SBP_EINVAL, "NULL adjoint workspace");
+  if ((std::uintptr_t)adj % 256) return fail(SBP_EINVAL, "adjoint workspace must be 256-byte aligned");
+  if (bytes < need) return fail(SBP_ENOMEM, "adjoint workspace too small: %zu < %zu bytes", bytes, need);
+  return SBP_OK;
+}
+
+// out = L^T lam (dense 9 fields in, dense 9 fields out)
+template <typename T>
+int do_adjoint_rhs(sbp_ctx* h, const void* lam, void* out, char* adj) {
+  int rc = prepare_bounds(h);
+  if (rc) return rc;
+  const AdjLayout L = adj_layout(h, 0, 1);
+  const StageArgs<T> base = stage_args<T>(h);
+  AdjArgs<T> a = adj_args<T>(h, adj, L);
+  if ((rc = copy_in(h, adj + L.dqb, lam, 9, hipMemcpyDeviceToDevice))) return rc;
+  HIPCHK(launch_fill<T>(a.qb, 9 * h->field, T(0), h->stream));
+  a.a = T(1);
+  a.b = T(0);
+  a.dt = T(1);
+  HIPCHK(launch_adj_pre<T>(a, h->stream));
+  if ((rc = stage_explicit<T>(h, base, 0, 1.0, 0.0, a.y, (T*)(adj + L.st), (T*)(adj + L.r), true, base.coef, false,
+                              false)))
+    return rc;
+  HIPCHK(launch_adj_post<T>(a, h->stream));
+  return copy_out(h, out, adj + L.qb, 9, hipMemcpyDeviceToDevice);
+}
+
+// Misfit gradient: a forward run of nsteps from the current state that keeps
+// checkpoints, then the reverse sweep block by block (each block recomputed
+// from its checkpoint, each step's stage inputs recomputed from its state).
+template <typename T>
+int do_gradient(sbp_ctx* h, int nsteps, double dt, const T* res, int every, char* adj, void* grad_out,
+                void* qbar_out) {
+  int rc = prepare_bounds(h);
+  if (rc) return rc;
+  const AdjLayout L = adj_layout(h, nsteps, every);
+  const StageArgs<T> base = stage_args<T>(h);
+  AdjArgs<T> a = adj_args<T>(h, adj, L);
+  const std::size_t F9 = 9 * h->field;
+  T* ck = (T*)(adj + L.ck);
+  T* blk = (T*)(adj + L.blk);
+  T* st = (T*)(adj + L.st);
+  T* const S[4] = {st, st + F9, st + 2 * F9, st + 3 * F9};
+  T* spare = st + 4 * F9;
+  T* dqs = (T*)(adj + L.dqs);
+  T* rbuf = (T*)(adj + L.r);
+  T* cu = (T*)(adj + L.cu);
+  T* state = (T*)(h->ws + (h->cur ? h->off_qb : h->off_qa));
+  const double t0 = h->t;
+  const std::size_t bytes9 = F9 * sizeof(T);
+
+  // forward pass with checkpoints (ping-pong through the y and r buffers)
+  T* X = a.y;
+  T* Y = rbuf;
+  HIPCHK(hipMemcpyAsync(X, state, bytes9, hipMemcpyDeviceToDevice, h->stream));
+  for (int n = 0; n < nsteps; ++n) {
+    if (n % L.every == 0)
+      HIPCHK(hipMemcpyAsync(ck + (std::size_t)(n / L.every) * F9, X, bytes9, hipMemcpyDeviceToDevice, h->stream));
+    if ((rc = step_explicit<T>(h, base, t0 + n * dt, dt, X, S, Y, dqs))) return rc;
+    std::swap(X, Y);
+  }
+  HIPCHK(hipMemcpyAsync(state, X, bytes9, hipMemcpyDeviceToDevice, h->stream));
+
+  // unit material (lambda/J = 0, mu/J = 1, 1/(rho J) = 1), J, zeroed accumulators
+  HIPCHK(hipMemcpyAsync(cu, h->ws + h->off_coef, 9 * h->field * sizeof(T), hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(launch_fill<T>(cu + 9 * h->field, h->field, T(0), h->stream));
+  HIPCHK(launch_fill<T>(cu + 10 * h->field, 2 * h->field, T(1), h->stream));
+  {
+    std::vector<T> jt(h->g.n);
+    for (std::size_t o = 0; o < h->g.n; ++o) jt[o] = (T)h->J[o];
+    if ((rc = copy_in(h, adj + L.jac, jt.data(), 1, hipMemcpyHostToDevice))) return rc;
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  HIPCHK(launch_fill<T>(a.qb, F9, T(0), h->stream));
+  HIPCHK(launch_fill<T>(a.grad, 3 * h->field, T(0), h->stream));
+  const long long* roff = (const long long*)(h->ws + h->off_rec);
+
+  // reverse sweep
+  for (int c = L.nck - 1; c >= 0; --c) {
+    const int n0 = c * L.every, n1 = std::min(nsteps, n0 + L.every);
+    HIPCHK(hipMemcpyAsync(blk, ck + (std::size_t)c * F9, bytes9, hipMemcpyDeviceToDevice, h->stream));
+    for (int n = n0; n < n1 - 1; ++n)
+      if ((rc = step_explicit<T>(h, base, t0 + n * dt, dt, blk + (std::size_t)(n - n0) * F9, S,
+                                 blk + (std::size_t)(n - n0 + 1) * F9, dqs)))
+        return rc;
+    for (int n = n1 - 1; n >= n0; --n) {
+      HIPCHK(launch_adj_inject<T>(a.qb, h->field, roff, h->nrec, res + (std::size_t)n * h->nrec * 3, h->stream));
+      const T* qn = blk + (std::size_t)(n - n0) * F9;
+      if ((rc = step_explicit<T>(h, base, t0 + n * dt, dt, qn, S, spare, dqs))) return rc;
+      for (int k = 4; k >= 0; --k) {
+        a.a = k == 4 ? T(0) : (T)kRkA[k + 1];
+        a.b = (T)kRkB[k];
+        a.dt = (T)dt;
+        HIPCHK(launch_adj_pre<T>(a, h->stream));
+        if ((rc = stage_explicit<T>(h, base, 0, 1.0, 0.0, a.y, spare, rbuf, true, base.coef, false, false))) return rc;
+        HIPCHK(launch_adj_post<T>(a, h->stream));
+        const T* qs = k == 0 ? qn : S[k - 1];
+        if ((rc = stage_explicit<T>(h, base, 0, 1.0, 0.0, qs, spare, rbuf, true, cu, false, false))) return rc;
+        a.qs = qs;
+        HIPCHK(launch_adj_grad<T>(a, h->stream));
+      }
+    }
+  }
+  if ((rc = copy_out(h, grad_out, adj + L.grad, 3, hipMemcpyDeviceToDevice))) return rc;
+  if (qbar_out && (rc = copy_out(h, qbar_out, adj + L.qb, 9, hipMemcpyDeviceToDevice))) return rc;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->t = t0 + nsteps * dt;
+  h->steps += nsteps;
+  return SBP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1206,6 +1427,38 @@ int sbp_rhs(sbp_handle h, void* out_device, double t) {
   if (!h || !out_device) return fail(SBP_EINVAL, "NULL argument");
   if (!h->have_material) return fail(SBP_ESTATE, "sbp_set_material has not been called");
   return h->dtype == SBP_F32 ? do_rhs<float>(h, out_device, t) : do_rhs<double>(h, out_device, t);
+}
+
+int sbp_adjoint_bytes(sbp_handle h, int nsteps, int every, size_t* bytes) {
+  if (!h || !bytes) return fail(SBP_EINVAL, "NULL argument");
+  if (nsteps < 0 || (nsteps > 0 && every < 1)) return fail(SBP_EINVAL, "need nsteps >= 0 and every >= 1");
+  *bytes = adj_layout(h, nsteps, every).total;
+  return SBP_OK;
+}
+
+int sbp_adjoint_rhs(sbp_handle h, const void* lam_device, void* out_device, void* adj_ws, size_t adj_bytes) {
+  if (!h || !lam_device || !out_device) return fail(SBP_EINVAL, "NULL argument");
+  if (!h->have_material) return fail(SBP_ESTATE, "sbp_set_material has not been called");
+  int rc = check_adj_ws(adj_ws, adj_bytes, adj_layout(h, 0, 1).total);
+  if (rc) return rc;
+  return h->dtype == SBP_F32 ? do_adjoint_rhs<float>(h, lam_device, out_device, (char*)adj_ws)
+                             : do_adjoint_rhs<double>(h, lam_device, out_device, (char*)adj_ws);
+}
+
+int sbp_gradient(sbp_handle h, int nsteps, double dt, const void* residual_device, int every, void* adj_ws,
+                 size_t adj_bytes, void* grad_device, void* qbar_device) {
+  if (!h || !residual_device || !grad_device) return fail(SBP_EINVAL, "NULL argument");
+  if (!h->have_material) return fail(SBP_ESTATE, "sbp_set_material has not been called");
+  if (h->nrec <= 0) return fail(SBP_ESTATE, "no receivers: call sbp_record first");
+  if (nsteps < 1 || every < 1 || !(dt > 0) || !std::isfinite(dt))
+    return fail(SBP_EINVAL, "need nsteps >= 1, every >= 1 and dt > 0");
+  int rc = check_adj_ws(adj_ws, adj_bytes, adj_layout(h, nsteps, every).total);
+  if (rc) return rc;
+  return h->dtype == SBP_F32
+             ? do_gradient<float>(h, nsteps, dt, (const float*)residual_device, every, (char*)adj_ws, grad_device,
+                                  qbar_device)
+             : do_gradient<double>(h, nsteps, dt, (const double*)residual_device, every, (char*)adj_ws,
+                                   grad_device, qbar_device);
 }
 
 int sbp_energy(sbp_handle h, double* E) {

@@ -58,6 +58,9 @@ def lib():
             "sbp_autotune": [c_void_p, c_int, P(c_int), P(c_int), P(c_double)],
             "sbp_profile": [c_void_p, P(c_double), P(c_double), P(ctypes.c_longlong), P(ctypes.c_longlong)],
             "sbp_destroy": [c_void_p],
+            "sbp_adjoint_bytes": [c_void_p, c_int, c_int, P(c_size_t)],
+            "sbp_adjoint_rhs": [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t],
+            "sbp_gradient": [c_void_p, c_int, c_double, c_void_p, c_int, c_void_p, c_size_t, c_void_p, c_void_p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -193,6 +196,21 @@ def sbp_destroy(h):
     _check(lib().sbp_destroy(h))
 
 
+def sbp_adjoint_bytes(h, nsteps, every):
+    n = ctypes.c_size_t(0)
+    _check(lib().sbp_adjoint_bytes(h, int(nsteps), int(every), ctypes.byref(n)))
+    return n.value
+
+
+def sbp_adjoint_rhs(h, lam_ptr, out_ptr, ws_ptr, ws_bytes):
+    _check(lib().sbp_adjoint_rhs(h, lam_ptr, out_ptr, ws_ptr, int(ws_bytes)))
+
+
+def sbp_gradient(h, nsteps, dt, res_ptr, every, ws_ptr, ws_bytes, grad_ptr, qbar_ptr=None):
+    _check(lib().sbp_gradient(h, int(nsteps), float(dt), res_ptr, int(every), ws_ptr, int(ws_bytes), grad_ptr,
+                              qbar_ptr))
+
+
 # ---- convenience wrapper -----------------------------------------------------
 
 class Solver:
@@ -287,6 +305,41 @@ class Solver:
 
     def time(self):
         return sbp_time(self.h)
+
+    def _adjoint_ws(self, nbytes):
+        """A 256-byte aligned device buffer of at least nbytes (kept and reused)."""
+        if getattr(self, "_adj", None) is None or self._adj_bytes < nbytes:
+            self._adj = None
+            self._adj = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=self.device)
+            self._adj_bytes = nbytes
+        return (self._adj.data_ptr() + 255) // 256 * 256
+
+    def adjoint_rhs(self, lam):
+        """L^T lam for a (9, ns, nr, nq) device tensor lam."""
+        lam = lam.to(device=self.device, dtype=self.tdtype).contiguous()
+        if lam.numel() != 9 * self.n:
+            raise ValueError("lam must hold 9 * n values")
+        nbytes = sbp_adjoint_bytes(self.h, 0, 1)
+        ws = self._adjoint_ws(nbytes)
+        out = self.torch.empty((9,) + self.shape, dtype=self.tdtype, device=self.device)
+        sbp_adjoint_rhs(self.h, lam.data_ptr(), out.data_ptr(), ws, nbytes)
+        return out
+
+    def gradient(self, nsteps, dt, residual, every=100, want_qbar=False):
+        """d chi / d (rho, lambda, mu) as a (3, ns, nr, nq) tensor (and d chi /
+        d Q0 if want_qbar) for the residual d chi / d traces of shape
+        (nsteps, nrec, 3), from the current state; the receivers are those of
+        the last record() call."""
+        res = residual.to(device=self.device, dtype=self.tdtype).contiguous()
+        if self.traces is None or res.numel() != nsteps * self.traces.shape[1] * 3:
+            raise ValueError("residual must have shape (nsteps, nrec, 3) for the receivers of record()")
+        nbytes = sbp_adjoint_bytes(self.h, nsteps, every)
+        ws = self._adjoint_ws(nbytes)
+        grad = self.torch.empty((3,) + self.shape, dtype=self.tdtype, device=self.device)
+        qbar = self.torch.empty((9,) + self.shape, dtype=self.tdtype, device=self.device) if want_qbar else None
+        sbp_gradient(self.h, nsteps, dt, res.data_ptr(), every, ws, nbytes, grad.data_ptr(),
+                     qbar.data_ptr() if want_qbar else None)
+        return (grad, qbar) if want_qbar else grad
 
     def close(self):
         if getattr(self, "h", None) is not None:
