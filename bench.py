@@ -20,6 +20,11 @@ cpu_baseline times the CPU oracle on a bounded sample of the same workload.
 `--workload batched` measures the batched-shots workload instead (32 cubes
 of uneven size, orders 4 and 6, one sbp_step_batch call): shots per second
 for `steps` steps per shot, beside the same shots stepped one after another.
+
+`--workload adjoint` measures the material gradient (sbp_gradient): the
+topo_layer block at 129^3, order 6, FP32, a model and a target model with 5 %
+smooth perturbations of rho, lambda and mu, 64 receivers, 1500 steps with a
+checkpoint every 100 steps; gradients per second, beside the forward run.
 """
 import argparse
 import hashlib
@@ -41,11 +46,16 @@ PROFILE = os.path.join(ROOT, "profiles", "stage_kernel_topo_layer_257x257x193.md
 CSRC = os.path.join(ROOT, "paper_2011_02600_amd", "csrc")
 
 
+# sources that decide the stage kernel's code, launch shape and data layout
+STAGE_SOURCES = ("api.cpp", "internal.hpp", "kernels.hip", "kernels.hpp", "penalty.hpp")
+
+
 def kernel_sha():
-    """sha256 (16 hex digits) of the library sources: kernels, tiling and layout."""
+    """sha256 (16 hex digits) of the library sources behind the stage kernel:
+    its code, tiling and layout."""
     h = hashlib.sha256()
     for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".hpp", ".cpp")):
+        if name in STAGE_SOURCES:
             with open(os.path.join(CSRC, name), "rb") as f:
                 h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()[:16]
@@ -95,6 +105,82 @@ def cpu_baseline(wl, order=6, nstages=2):
     return {"value": nodes * nstages / el / 1e6, "unit": "Mpts*stage/s", "cores": cores, "kind": "oracle",
             "sample": "%d Runge-Kutta stages (RHS + update) of the full %dx%dx%d workload in float64 numpy, "
                       "%.1f s; mesh/metric setup excluded" % ((nstages,) + tuple(Q.shape[1:][::-1]) + (el,))}
+
+
+def run_adjoint(args, W, sbp, torch, np, dev):
+    """Misfit gradient of the 129^3 adjoint workload: the target traces and
+    the model traces come from forward runs (untimed); the timed region is
+    one sbp_gradient call (its checkpointed forward run, the block
+    recomputations and the reverse sweep), beside one plain forward run."""
+    steps, every = args.adjoint_steps, args.every
+    print("bench: generating the adjoint workload", file=sys.stderr, flush=True)
+    wl = W.adjoint_case()
+    ns, nr, nq = wl["xyz"].shape[1:]
+    s = sbp.Solver(wl["xyz"], order=6, dtype="f32", gamma=wl["gamma"], device=dev)
+    s.add_source(wl["src_xi"], wl["src_M"], sbp.SBP_STF_RICKER, wl["src_f0"], wl["src_t0"])
+    s.set_material(*wl["model"])
+    ty, zc, _ = s.autotune()
+    dt = wl["dt"]
+    Q0 = torch.zeros((9, ns, nr, nq), dtype=torch.float32, device=dev)
+
+    def forward(mat):
+        s.set_material(*mat)
+        s.set_state(Q0, 0.0)
+        tr = s.record(wl["receivers"], steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(steps, dt)
+        torch.cuda.synchronize()
+        return tr.clone(), time.perf_counter() - t0
+
+    target, _ = forward(wl["target"])
+    traces, _ = forward(wl["model"])
+    _, fwd_s = forward(wl["model"])
+    res = traces - target
+    misfit = 0.5 * float((res.double() ** 2).sum())
+    for _ in range(args.warmup_grad):
+        s.set_state(Q0, 0.0)
+        s.gradient(min(steps, 2 * every), dt, res[:min(steps, 2 * every)], every)
+    s.set_state(Q0, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    grad = s.gradient(steps, dt, res, every)
+    torch.cuda.synchronize()
+    grad_s = time.perf_counter() - t0
+    g = grad.double()
+    if not bool(torch.isfinite(g).all()):
+        raise RuntimeError("non-finite gradient")
+    nbytes = sbp.sbp_adjoint_bytes(s.h, steps, every)
+    print("bench: gradient of %d steps in %.3f s, forward %.3f s" % (steps, grad_s, fwd_s), file=sys.stderr,
+          flush=True)
+    s.close()
+    out = {
+        "metric": "gradients/s (d misfit / d (rho, lambda, mu), 129^3 order-6 FP32 curvilinear, %d steps)" % steps,
+        "value": round(1.0 / grad_s, 4),
+        "unit": "gradients/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup_grad,
+        "ms_per_step": round(1e3 * grad_s / steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "adjoint: topo_layer block %dx%dx%d (order 6), model and target model = layered "
+                               "medium x (1 + smooth seeded perturbations of rho, lambda, mu, max 5 %%), "
+                               "64 surface receivers, Ricker moment source, CFL 0.5, misfit = 1/2 L2 of "
+                               "the trace residual" % (nq, nr, ns),
+                   "grid": [nq, nr, ns], "nodes": nq * nr * ns, "checkpoint_every": every, "dt": dt,
+                   "launch": {"ty": ty, "zchunk": zc},
+                   "adjoint_workspace_bytes": nbytes},
+        "gradient_s": round(grad_s, 4),
+        "forward_s": round(fwd_s, 4),
+        "gradient_over_forward": round(grad_s / fwd_s, 3),
+        "misfit": misfit,
+        "grad_max_abs": [float(g[i].abs().max()) for i in range(3)],
+    }
+    print(json.dumps(out), flush=True)
 
 
 def run_batched(args, W, sbp, torch, np, dev):
@@ -183,7 +269,10 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--order", type=int, default=6, choices=[2, 3, 4, 5, 6],
                     help="interior order of the topo_layer run (the headline workload is order 6)")
-    ap.add_argument("--workload", default="topo_layer", choices=["topo_layer", "batched"])
+    ap.add_argument("--workload", default="topo_layer", choices=["topo_layer", "batched", "adjoint"])
+    ap.add_argument("--adjoint-steps", type=int, default=1500, help="steps of the adjoint workload")
+    ap.add_argument("--every", type=int, default=100, help="checkpoint interval of the adjoint workload")
+    ap.add_argument("--warmup-grad", type=int, default=1, help="untimed short gradient runs (adjoint workload)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (x4) for HBM counter calibration")
     args = ap.parse_args()
@@ -211,6 +300,9 @@ def main():
         return
     if args.workload == "batched":
         run_batched(args, W, sbp, torch, np, dev)
+        return
+    if args.workload == "adjoint":
+        run_adjoint(args, W, sbp, torch, np, dev)
         return
     print("bench: generating workload", file=sys.stderr, flush=True)
     # the interior symbols of orders 2 and 4 reach larger magnitudes than

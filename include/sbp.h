@@ -202,7 +202,7 @@ int sbp_rhs(sbp_handle h, void* out_device, double t);
  *
  * sbp_adjoint_bytes: bytes of the caller-owned adjoint workspace that
  * sbp_gradient needs for nsteps steps with a checkpoint every `every` steps:
- * ceil(nsteps / every) + every saved states plus about 100 grid functions
+ * ceil(nsteps / every) + 5 every saved states plus about 100 grid functions
  * (nsteps = 0: the size sbp_adjoint_rhs needs).  every is clamped to
  * [1, nsteps].
  */
@@ -228,7 +228,7 @@ int sbp_adjoint_rhs(sbp_handle h, const void* lam_device, void* out_device, void
  * at the current time, runs nsteps steps of size dt (sources included,
  * receiver traces not recorded), keeping a checkpoint every `every` steps in
  * adj_ws, then the reverse sweep: each block of steps is recomputed from
- * its checkpoint, each step's stage inputs from its state.  Writes d chi /
+ * its checkpoint, keeping the inputs of every stage of the block.  Writes d chi /
  * d (rho, lambda, mu) at every node to grad_device (3 dense grid functions:
  * rho, then lambda, then mu, with the other two held fixed) and, if
  * qbar_device is not NULL, d chi / d Q0 (9 dense grid functions).  The

@@ -12,7 +12,8 @@
 //   L^T l = -W L_v(W^{-1} l) + Bd W^{-1} l + P^T l,
 // P the face-local penalty blocks.  L_v(W^{-1} l) is one forward
 // right-hand-side evaluation with the penalties off (the stage kernel); the
-// kernels here apply W^{-1} (adj_pre), and -W, Bd and P^T (adj_post).
+// kernels here apply W^{-1} (adj_pre), -W (adj_post, every node) and Bd and
+// P^T (adj_face, face nodes only, one launch per axis).
 //
 // The material enters the right-hand side pointwise: 1/(rho J) times the
 // flux divergence dv, lambda/J and mu/J times the velocity gradient terms,
@@ -72,26 +73,6 @@ __device__ __forceinline__ Node node_of(const AdjArgs<T>& A, long long n) {
   d.k = (int)(t / A.nr);
   d.o = A.nm(d.i, d.j, d.k);
   return d;
-}
-
-// index of the node in the coefficient array of face f
-template <typename T>
-__device__ __forceinline__ std::size_t face_index(const AdjArgs<T>& A, int f, const Node& d) {
-  if (f < 2) return (std::size_t)d.k * A.nr + d.j;
-  if (f < 4) return (std::size_t)d.k * A.nq + d.i;
-  return (std::size_t)d.j * A.nq + d.i;
-}
-
-template <typename T>
-__device__ __forceinline__ bool on_face(const AdjArgs<T>& A, int f, const Node& d) {
-  switch (f) {
-    case 0: return d.i == 0;
-    case 1: return d.i == A.nq - 1;
-    case 2: return d.j == 0;
-    case 3: return d.j == A.nr - 1;
-    case 4: return d.k == 0;
-    default: return d.k == A.ns - 1;
-  }
 }
 
 template <typename T>
@@ -154,53 +135,6 @@ __global__ void adj_post_kernel(const AdjArgs<T> A) {
     out[6] = -Hn * r[6] / muJ;
     out[7] = -Hn * r[7] / muJ;
     out[8] = -Hn * r[8] / muJ;
-    if (nd.i == 0 || nd.i == A.nq - 1 || nd.j == 0 || nd.j == A.nr - 1 || nd.k == 0 || nd.k == A.ns - 1) {
-      T y[9], l[9];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        y[c] = A.y[c * F + o];
-        l[c] = A.dqb[c * F + o];
-      }
-      for (int f = 0; f < 6; ++f) {
-        if (!on_face(A, f, nd)) continue;
-        const int xi = f >> 1;
-        const T sgn = (f & 1) ? T(1) : T(-1);
-        // B_xi: sign times the norm weights of the two other axes
-        const T bw = xi == 0 ? A.h[1] * wr * A.h[2] * ws : (xi == 1 ? A.h[0] * wq * A.h[2] * ws : A.h[0] * wq * A.h[1] * wr);
-        const T b = sgn * bw;
-        const T m0 = A.coef[(3 * xi) * F + o], m1 = A.coef[(3 * xi + 1) * F + o], m2 = A.coef[(3 * xi + 2) * F + o];
-        // Bd y: velocity rows take the flux of y_sigma, stress rows the
-        // transposed flux map of y_v
-        out[0] += b * (m0 * y[3] + m1 * y[6] + m2 * y[7]);
-        out[1] += b * (m0 * y[6] + m1 * y[4] + m2 * y[8]);
-        out[2] += b * (m0 * y[7] + m1 * y[8] + m2 * y[5]);
-        const T z0 = b * y[0], z1 = b * y[1], z2 = b * y[2];
-        out[3] += m0 * z0;
-        out[4] += m1 * z1;
-        out[5] += m2 * z2;
-        out[6] += m1 * z0 + m0 * z1;
-        out[7] += m2 * z0 + m0 * z2;
-        out[8] += m2 * z1 + m1 * z2;
-        // P^T l: column kk of the penalty block is its response to unit vector kk
-        T fc[kNumFaceCoef];
-        const std::size_t idx = face_index(A, f, nd);
-#pragma unroll
-        for (int kk = 0; kk < kNumFaceCoef; ++kk) fc[kk] = A.face[A.face_off[f] + idx + (std::size_t)kk * A.face_n[f]];
-        for (int kk = 0; kk < 9; ++kk) {
-          T ev[3] = {T(0), T(0), T(0)}, es[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-          if (kk < 3) ev[kk] = T(1);
-          else es[kk - 3] = T(1);
-          T rate[9];
-#pragma unroll
-          for (int c = 0; c < 9; ++c) rate[c] = T(0);
-          face_penalty(fc, A.gamma[f], sgn, A.traction[f] != 0, ev, es, rate);
-          T s = T(0);
-#pragma unroll
-          for (int c = 0; c < 9; ++c) s += rate[c] * l[c];
-          out[kk] += s;
-        }
-      }
-    }
 #pragma unroll
     for (int c = 0; c < 9; ++c) A.qb[c * F + o] += A.dt * out[c];
   }
@@ -227,59 +161,125 @@ __global__ void adj_grad_kernel(const AdjArgs<T> A) {
     const T div = T(0.5) * (ru[3] + ru[4] + ru[5]);
     T g1 = iJ * div * (l[3] + l[4] + l[5]);
     T g2 = iJ * (l[3] * ru[3] + l[4] * ru[4] + l[5] * ru[5] + l[6] * ru[6] + l[7] * ru[7] + l[8] * ru[8]);
-    if (nd.i == 0 || nd.i == A.nq - 1 || nd.j == 0 || nd.j == A.nr - 1 || nd.k == 0 || nd.k == A.ns - 1) {
-      using D = Dual<T>;
-      D v[3], sg[6];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) v[c] = D(A.qs[c * F + o], T(0));
-#pragma unroll
-      for (int c = 0; c < 6; ++c) sg[c] = D(A.qs[(3 + c) * F + o], T(0));
-      const T rho = T(1) / (rJ * J);
-      for (int f = 0; f < 6; ++f) {
-        if (!on_face(A, f, nd)) continue;
-        T fc[kNumFaceCoef];
-        const std::size_t idx = face_index(A, f, nd);
-#pragma unroll
-        for (int kk = 0; kk < kNumFaceCoef; ++kk) fc[kk] = A.face[A.face_off[f] + idx + (std::size_t)kk * A.face_n[f]];
-        const T zp = fc[F_ZP], zs = fc[F_ZS], izp = fc[F_IZP], izs = fc[F_IZS], kr = fc[F_KR];
-        const T kap = kr * rho;
-        // derivatives of the face coefficients (Z_p = sqrt(rho (lambda + 2 mu)),
-        // Z_s = sqrt(rho mu), their inverses, kappa/rho, kappa lambda,
-        // kappa mu) with respect to rho, lambda, mu
-        T seed[3][kNumFaceCoef] = {};
-        seed[0][F_ZP] = zp / (T(2) * rho);
-        seed[0][F_ZS] = zs / (T(2) * rho);
-        seed[0][F_IZP] = -izp / (T(2) * rho);
-        seed[0][F_IZS] = -izs / (T(2) * rho);
-        seed[0][F_KR] = -kr / rho;
-        seed[1][F_ZP] = T(0.5) * rho * izp;
-        seed[1][F_IZP] = -T(0.5) * rho * izp * izp * izp;
-        seed[1][F_KL] = kap;
-        seed[2][F_ZP] = rho * izp;
-        seed[2][F_ZS] = T(0.5) * rho * izs;
-        seed[2][F_IZP] = -rho * izp * izp * izp;
-        seed[2][F_IZS] = -T(0.5) * rho * izs * izs * izs;
-        seed[2][F_KM] = kap;
-        const T sgn = (f & 1) ? T(1) : T(-1);
-        for (int p = 0; p < 3; ++p) {
-          D dfc[kNumFaceCoef], rate[9];
-#pragma unroll
-          for (int kk = 0; kk < kNumFaceCoef; ++kk) dfc[kk] = D(fc[kk], seed[p][kk]);
-#pragma unroll
-          for (int c = 0; c < 9; ++c) rate[c] = D(T(0), T(0));
-          face_penalty(dfc, D(A.gamma[f], T(0)), D(sgn, T(0)), A.traction[f] != 0, v, sg, rate);
-          T s = T(0);
-#pragma unroll
-          for (int c = 0; c < 9; ++c) s += rate[c].d * l[c];
-          if (p == 0) g0 += s;
-          else if (p == 1) g1 += s;
-          else g2 += s;
-        }
-      }
-    }
     A.grad[0 * F + o] += A.dt * g0;
     A.grad[1 * F + o] += A.dt * g1;
     A.grad[2 * F + o] += A.dt * g2;
+  }
+}
+
+// Face terms of one axis xi: the nodes of faces 2 xi and 2 xi + 1 (disjoint,
+// so one launch per axis has no two threads on one node).  GRAD = false:
+// Bd y + P^T dqb added to qb (times dt); GRAD = true: the derivative of the
+// penalty with respect to the node's rho, lambda, mu (dual numbers, seeded
+// with the derivatives of the face coefficients) against dqb, added to grad.
+template <typename T, bool GRAD>
+__global__ void adj_face_kernel(const AdjArgs<T> A, int xi) {
+  const std::size_t F = A.field;
+  const std::size_t fn = xi == 0 ? (std::size_t)A.nr * A.ns : (xi == 1 ? (std::size_t)A.nq * A.ns
+                                                                        : (std::size_t)A.nq * A.nr);
+  const std::size_t t = blockIdx.x * (std::size_t)blockDim.x + threadIdx.x;
+  if (t >= 2 * fn) return;
+  const int side = t >= fn ? 1 : 0;
+  const int f = 2 * xi + side;
+  const std::size_t idx = t - side * fn;
+  Node nd;
+  if (xi == 0) {
+    nd.i = side ? A.nq - 1 : 0;
+    nd.j = (int)(idx % A.nr);
+    nd.k = (int)(idx / A.nr);
+  } else if (xi == 1) {
+    nd.i = (int)(idx % A.nq);
+    nd.j = side ? A.nr - 1 : 0;
+    nd.k = (int)(idx / A.nq);
+  } else {
+    nd.i = (int)(idx % A.nq);
+    nd.j = (int)(idx / A.nq);
+    nd.k = side ? A.ns - 1 : 0;
+  }
+  const long long o = A.nm(nd.i, nd.j, nd.k);
+  T fc[kNumFaceCoef];
+#pragma unroll
+  for (int kk = 0; kk < kNumFaceCoef; ++kk) fc[kk] = A.face[A.face_off[f] + idx + (std::size_t)kk * A.face_n[f]];
+  const T sgn = side ? T(1) : T(-1);
+  T l[9];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) l[c] = A.dqb[c * F + o];
+  if constexpr (!GRAD) {
+    T y[9], out[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) y[c] = A.y[c * F + o];
+    const T wq = norm_w(A, nd.i, A.nq), wr = norm_w(A, nd.j, A.nr), ws = norm_w(A, nd.k, A.ns);
+    // B_xi: sign times the norm weights of the two other axes
+    const T bw = xi == 0 ? A.h[1] * wr * A.h[2] * ws : (xi == 1 ? A.h[0] * wq * A.h[2] * ws : A.h[0] * wq * A.h[1] * wr);
+    const T b = sgn * bw;
+    const T m0 = A.coef[(3 * xi) * F + o], m1 = A.coef[(3 * xi + 1) * F + o], m2 = A.coef[(3 * xi + 2) * F + o];
+    // Bd y: velocity rows take the flux of y_sigma, stress rows the
+    // transposed flux map of y_v
+    out[0] = b * (m0 * y[3] + m1 * y[6] + m2 * y[7]);
+    out[1] = b * (m0 * y[6] + m1 * y[4] + m2 * y[8]);
+    out[2] = b * (m0 * y[7] + m1 * y[8] + m2 * y[5]);
+    const T z0 = b * y[0], z1 = b * y[1], z2 = b * y[2];
+    out[3] = m0 * z0;
+    out[4] = m1 * z1;
+    out[5] = m2 * z2;
+    out[6] = m1 * z0 + m0 * z1;
+    out[7] = m2 * z0 + m0 * z2;
+    out[8] = m2 * z1 + m1 * z2;
+    // P^T l: column kk of the penalty block is its response to unit vector kk
+    for (int kk = 0; kk < 9; ++kk) {
+      T ev[3] = {T(0), T(0), T(0)}, es[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+      if (kk < 3) ev[kk] = T(1);
+      else es[kk - 3] = T(1);
+      T rate[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) rate[c] = T(0);
+      face_penalty(fc, A.gamma[f], sgn, A.traction[f] != 0, ev, es, rate);
+      T s = T(0);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) s += rate[c] * l[c];
+      out[kk] += s;
+    }
+#pragma unroll
+    for (int c = 0; c < 9; ++c) A.qb[c * F + o] += A.dt * out[c];
+  } else {
+    using D = Dual<T>;
+    D v[3], sg[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) v[c] = D(A.qs[c * F + o], T(0));
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sg[c] = D(A.qs[(3 + c) * F + o], T(0));
+    const T rho = T(1) / (A.coef[11 * F + o] * A.jac[o]);
+    const T zp = fc[F_ZP], zs = fc[F_ZS], izp = fc[F_IZP], izs = fc[F_IZS], kr = fc[F_KR];
+    const T kap = kr * rho;
+    // derivatives of the face coefficients (Z_p = sqrt(rho (lambda + 2 mu)),
+    // Z_s = sqrt(rho mu), their inverses, kappa/rho, kappa lambda, kappa mu)
+    // with respect to rho, lambda, mu
+    T seed[3][kNumFaceCoef] = {};
+    seed[0][F_ZP] = zp / (T(2) * rho);
+    seed[0][F_ZS] = zs / (T(2) * rho);
+    seed[0][F_IZP] = -izp / (T(2) * rho);
+    seed[0][F_IZS] = -izs / (T(2) * rho);
+    seed[0][F_KR] = -kr / rho;
+    seed[1][F_ZP] = T(0.5) * rho * izp;
+    seed[1][F_IZP] = -T(0.5) * rho * izp * izp * izp;
+    seed[1][F_KL] = kap;
+    seed[2][F_ZP] = rho * izp;
+    seed[2][F_ZS] = T(0.5) * rho * izs;
+    seed[2][F_IZP] = -rho * izp * izp * izp;
+    seed[2][F_IZS] = -T(0.5) * rho * izs * izs * izs;
+    seed[2][F_KM] = kap;
+    for (int p = 0; p < 3; ++p) {
+      D dfc[kNumFaceCoef], rate[9];
+#pragma unroll
+      for (int kk = 0; kk < kNumFaceCoef; ++kk) dfc[kk] = D(fc[kk], seed[p][kk]);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) rate[c] = D(T(0), T(0));
+      face_penalty(dfc, D(A.gamma[f], T(0)), D(sgn, T(0)), A.traction[f] != 0, v, sg, rate);
+      T s = T(0);
+#pragma unroll
+      for (int c = 0; c < 9; ++c) s += rate[c].d * l[c];
+      A.grad[p * F + o] += A.dt * s;
+    }
   }
 }
 
@@ -311,15 +311,28 @@ hipError_t launch_adj_pre(const AdjArgs<T>& a, hipStream_t st) {
   hipLaunchKernelGGL(adj_pre_kernel<T>, dim3(node_blocks(a)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
+template <typename T, bool GRAD>
+hipError_t launch_faces(const AdjArgs<T>& a, hipStream_t st) {
+  const std::size_t fn[3] = {(std::size_t)a.nr * a.ns, (std::size_t)a.nq * a.ns, (std::size_t)a.nq * a.nr};
+  for (int xi = 0; xi < 3; ++xi) {
+    hipLaunchKernelGGL((adj_face_kernel<T, GRAD>), dim3((unsigned)((2 * fn[xi] + 255) / 256)), dim3(256), 0, st, a,
+                       xi);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 template <typename T>
 hipError_t launch_adj_post(const AdjArgs<T>& a, hipStream_t st) {
   hipLaunchKernelGGL(adj_post_kernel<T>, dim3(node_blocks(a)), dim3(256), 0, st, a);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : launch_faces<T, false>(a, st);
 }
 template <typename T>
 hipError_t launch_adj_grad(const AdjArgs<T>& a, hipStream_t st) {
   hipLaunchKernelGGL(adj_grad_kernel<T>, dim3(node_blocks(a)), dim3(256), 0, st, a);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  return e != hipSuccess ? e : launch_faces<T, true>(a, st);
 }
 template <typename T>
 hipError_t launch_adj_inject(T* qb, std::size_t field, const long long* off, int nrec, const T* res,

@@ -921,10 +921,11 @@ int do_autotune(sbp_ctx* h, int reps, int* best_ty, int* best_zchunk, double* be
 
 // ---- discrete adjoint ---------------------------------------------------------
 // Layout of the caller's adjoint workspace (byte offsets): checkpoints of the
-// state every `every` steps, the states of one block of steps, the stage
-// inputs of one step, the forward Runge-Kutta register, the adjoint state and
-// register, W^{-1} dQb, a right-hand-side buffer, the unit-material
-// coefficients, J and the three gradient fields.
+// state every `every` steps, the state and the inputs of stages 2-5 of every
+// step of one block of steps, the stage outputs of one step, the forward
+// Runge-Kutta register, the adjoint state and register, W^{-1} dQb, a
+// right-hand-side buffer, the unit-material coefficients, J and the three
+// gradient fields.
 struct AdjLayout {
   std::size_t ck = 0, blk = 0, st = 0, dqs = 0, qb = 0, dqb = 0, y = 0, r = 0, cu = 0, jac = 0, grad = 0, total = 0;
   int nck = 0, every = 0;
@@ -942,7 +943,7 @@ AdjLayout adj_layout(const sbp_ctx* h, int nsteps, int every) {
     return at;
   };
   L.ck = take((std::size_t)L.nck * 9 * F);
-  L.blk = take((std::size_t)L.every * 9 * F);
+  L.blk = take((std::size_t)L.every * 5 * 9 * F);
   L.st = take(5 * 9 * F);
   L.dqs = take(9 * F);
   L.qb = take(9 * F);
@@ -1056,7 +1057,7 @@ int do_adjoint_rhs(sbp_ctx* h, const void* lam, void* out, char* adj) {
 
 // Misfit gradient: a forward run of nsteps from the current state that keeps
 // checkpoints, then the reverse sweep block by block (each block recomputed
-// from its checkpoint, each step's stage inputs recomputed from its state).
+// from its checkpoint, keeping every stage input of the block).
 template <typename T>
 int do_gradient(sbp_ctx* h, int nsteps, double dt, const T* res, int every, char* adj, void* grad_out,
                 void* qbar_out) {
@@ -1107,15 +1108,16 @@ int do_gradient(sbp_ctx* h, int nsteps, double dt, const T* res, int every, char
   // reverse sweep
   for (int c = L.nck - 1; c >= 0; --c) {
     const int n0 = c * L.every, n1 = std::min(nsteps, n0 + L.every);
+    // slot n - n0 of the block: the state of step n, then its stage inputs 2-5
+    auto slot = [&](int n) { return blk + (std::size_t)(n - n0) * 5 * F9; };
     HIPCHK(hipMemcpyAsync(blk, ck + (std::size_t)c * F9, bytes9, hipMemcpyDeviceToDevice, h->stream));
-    for (int n = n0; n < n1 - 1; ++n)
-      if ((rc = step_explicit<T>(h, base, t0 + n * dt, dt, blk + (std::size_t)(n - n0) * F9, S,
-                                 blk + (std::size_t)(n - n0 + 1) * F9, dqs)))
+    for (int n = n0; n < n1; ++n) {
+      T* const Sn[4] = {slot(n) + F9, slot(n) + 2 * F9, slot(n) + 3 * F9, slot(n) + 4 * F9};
+      if ((rc = step_explicit<T>(h, base, t0 + n * dt, dt, slot(n), Sn, n + 1 < n1 ? slot(n + 1) : spare, dqs)))
         return rc;
+    }
     for (int n = n1 - 1; n >= n0; --n) {
       HIPCHK(launch_adj_inject<T>(a.qb, h->field, roff, h->nrec, res + (std::size_t)n * h->nrec * 3, h->stream));
-      const T* qn = blk + (std::size_t)(n - n0) * F9;
-      if ((rc = step_explicit<T>(h, base, t0 + n * dt, dt, qn, S, spare, dqs))) return rc;
       for (int k = 4; k >= 0; --k) {
         a.a = k == 4 ? T(0) : (T)kRkA[k + 1];
         a.b = (T)kRkB[k];
@@ -1123,7 +1125,7 @@ int do_gradient(sbp_ctx* h, int nsteps, double dt, const T* res, int every, char
         HIPCHK(launch_adj_pre<T>(a, h->stream));
         if ((rc = stage_explicit<T>(h, base, 0, 1.0, 0.0, a.y, spare, rbuf, true, base.coef, false, false))) return rc;
         HIPCHK(launch_adj_post<T>(a, h->stream));
-        const T* qs = k == 0 ? qn : S[k - 1];
+        const T* qs = slot(n) + (std::size_t)k * F9;
         if ((rc = stage_explicit<T>(h, base, 0, 1.0, 0.0, qs, spare, rbuf, true, cu, false, false))) return rc;
         a.qs = qs;
         HIPCHK(launch_adj_grad<T>(a, h->stream));

@@ -233,3 +233,29 @@ def batched_shots(nshots=32, seed=0, h=0.05, cfl=0.5, corr_cells=10, amp=0.1, f0
                           src_xi=src, src_M=(0.0, 0.0, 0.0, 1.0, 0.0, 0.0), src_f0=f0, src_t0=1.2 / f0,
                           receivers=np.array(rec, dtype=np.int32)))
     return shots
+
+
+def adjoint_case(n=129, seed=0, amp=0.05, corr_cells=10, cfl=0.5, nrec_side=8):
+    """Material-gradient workload: the topo_layer block at n^3 points (order
+    6), a model and a target model that are the layered medium times 1 + d,
+    with separate smooth seeded perturbations d (grf, max |d| = amp) of rho,
+    lambda and mu in each; nrec_side^2 surface receivers, the Ricker moment
+    source of topo_layer, zero initial state.  dt from the larger cp of the
+    two models.  Returns the topo_layer dict with model=(rho, cp, cs) and
+    target=(rho, cp, cs)."""
+    wl = topo_layer(nq=n, nr=n, ns=n, seed=seed, cfl=cfl, nrec_side=nrec_side)
+    rho0, cp0, cs0 = wl["rho"], wl["cp"], wl["cs"]
+    mu0 = rho0 * cs0 ** 2
+    lam0 = rho0 * cp0 ** 2 - 2 * mu0
+    shape = rho0.shape
+
+    def perturbed(s):
+        rho = rho0 * (1 + grf(shape, corr_cells, s, amp))
+        lam = lam0 * (1 + grf(shape, corr_cells, s + 1, amp))
+        mu = mu0 * (1 + grf(shape, corr_cells, s + 2, amp))
+        return rho, np.sqrt((lam + 2 * mu) / rho), np.sqrt(mu / rho)
+
+    model = perturbed(1000 * seed + 11)
+    target = perturbed(1000 * seed + 21)
+    wl.update(model=model, target=target, dt=cfl_dt(wl["xyz"], np.maximum(model[1], target[1]), cfl))
+    return wl
