@@ -90,6 +90,7 @@ def mms_error(order, n, warped, gamma, T=0.05, cfl=0.25):
     (3, (9, 17, 33), True),
     (5, (13, 19, 25, 37), False),
     (5, (13, 19, 25, 37), True),
+    (7, (15, 21, 29, 41), False),
     (6, (13, 19, 25, 37), False),
     (6, (13, 19, 25, 37), True),
 ])
