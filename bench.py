@@ -267,7 +267,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ty", type=int, default=8)
     ap.add_argument("--zchunk", type=int, default=0)
-    ap.add_argument("--order", type=int, default=6, choices=[2, 3, 4, 5, 6],
+    ap.add_argument("--order", type=int, default=6, choices=[2, 3, 4, 5, 6, 7],
                     help="interior order of the topo_layer run (the headline workload is order 6)")
     ap.add_argument("--workload", default="topo_layer", choices=["topo_layer", "batched", "adjoint"])
     ap.add_argument("--adjoint-steps", type=int, default=1500, help="steps of the adjoint workload")

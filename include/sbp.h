@@ -90,8 +90,9 @@ int sbp_workspace_bytes(int nq, int nr, int ns, int order, int dtype, size_t* by
  *               precision (x_xi = D0 x with D0 = (D+ + D-)/2, J = det, and the
  *               conservative cofactor form of J dxi/dx); a non-positive
  *               Jacobian anywhere is SBP_EINVAL.
- *  order        interior order of accuracy of the upwind pair, 2 to 6
- *               (Table tab:upwind).  The boundary closures are accurate to
+ *  order        interior order of accuracy of the upwind pair, 2 to 7
+ *               (Table tab:upwind; 7 with SBP_F32 only, whose tiles fit
+ *               the LDS; 8 and 9 are SBP_EINVAL).  The boundary closures are accurate to
  *               order order / 2 (rounded down); the paper does not print
  *               them: the library constructs them from the SBP and upwind
  *               properties of Sec. 4.1, the entries those leave free fixed

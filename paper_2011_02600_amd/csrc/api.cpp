@@ -54,7 +54,7 @@ constexpr int kMaxRec = 65536;
 // kBatchSteps steps at a time; handles are grouped by (order, tile height)
 constexpr int kMaxBatch = 64;
 constexpr int kBatchSteps = 32;
-constexpr int kMaxGroups = 10;  // five orders x two tile heights
+constexpr int kMaxGroups = 12;  // six orders x two tile heights
 
 constexpr int kMaxPart = 1024;
 constexpr double kPi = 3.14159265358979323846;
@@ -118,7 +118,11 @@ struct sbp_ctx {
 namespace {
 
 int check_dims(int nq, int nr, int ns, int order, int dtype) {
-  if (order < 2 || order > 6) return fail(SBP_EINVAL, "order must be 2, 3, 4, 5 or 6 (got %d)", order);
+  if (order == 8 || order == 9)
+    return fail(SBP_EINVAL, "order %d is not supported: its 5-point halo does not fit the 8-row stage tiles", order);
+  if (order < 2 || order > 7) return fail(SBP_EINVAL, "order must be 2 to 7 (got %d)", order);
+  if (order == 7 && dtype == SBP_F64)
+    return fail(SBP_EINVAL, "order 7 runs in SBP_F32 only: its double-precision stage tiles exceed the LDS");
   if (dtype != SBP_F32 && dtype != SBP_F64) return fail(SBP_EINVAL, "dtype must be SBP_F32 or SBP_F64");
   const int mn = 2 * order;
   if (nq < mn || nr < mn || ns < mn)

@@ -15,7 +15,8 @@
 // with characteristic penalties has the smallest spectral radius (no larger
 // than the interior stencil's) with positive weights, at the simplest
 // rational of equal radius: order 3 A[1][2] = 1/2, order 5 A[2][4] = 1/4 and
-// A[3][4] = 1/2, order 6 A[4][5] = 101/125.  For interior order 2p + 1 the
+// A[3][4] = 1/2, order 6 A[4][5] = 101/125, order 7 A[5][6] = 2/3,
+// A[4][6] = A[3][6] = 0, A[4][5] = 3/5.  For interior order 2p + 1 the
 // boundary accuracy is p, as for 2p.  The system is solved with Householder
 // QR in long double.
 #include <cmath>
@@ -33,13 +34,14 @@ struct Row {
   int n;
 };
 
-// Table tab:upwind, orders 2 to 6: alpha_{-r} .. alpha_{q}.
+// Table tab:upwind, orders 2 to 7: alpha_{-r} .. alpha_{q}.
 const Row kTable[] = {
     {2, 0, {-3, 2, -1}, {2, 1, 2}, 3},
     {3, 1, {-1, -1, 1, -1}, {3, 2, 1, 6}, 4},
     {4, 1, {-1, -5, 3, -1, 1}, {4, 6, 2, 2, 12}, 5},
     {5, 2, {1, -1, -1, 1, -1, 1}, {20, 2, 3, 1, 4, 30}, 6},
     {6, 2, {1, -2, -7, 4, -1, 2, -1}, {30, 5, 12, 3, 2, 15, 60}, 7},
+    {7, 3, {-1, 1, -3, -1, 1, -3, 1, -1}, {105, 10, 5, 4, 1, 10, 15, 140}, 8},
 };
 
 // Corner-block entries A[i][j] = num/den left free by the accuracy conditions.
@@ -51,6 +53,10 @@ const FreeEntry kFree[] = {
     {5, 2, 4, 1, 4},
     {5, 3, 4, 1, 2},
     {6, 4, 5, 101, 125},
+    {7, 5, 6, 2, 3},
+    {7, 4, 6, 0, 1},
+    {7, 3, 6, 0, 1},
+    {7, 4, 5, 3, 5},
 };
 
 long double binom(int n, int k) {
@@ -103,7 +109,7 @@ bool build_closure(int order, Closure* out, const char** err) {
   for (const Row& t : kTable)
     if (t.order == order) row = &t;
   if (!row) {
-    *err = "unsupported order (2 to 6)";
+    *err = "unsupported order (2 to 7)";
     return false;
   }
   const int r = row->r;

@@ -6,9 +6,9 @@
 
 namespace sbp {
 
-// Largest closure block (interior order 6: 6 rows x 10 columns).
-constexpr int kMaxM = 6;
-constexpr int kMaxCols = 10;
+// Largest closure block (interior order 7: 7 rows x 11 columns).
+constexpr int kMaxM = 7;
+constexpr int kMaxCols = 11;
 constexpr int kMaxSources = 4;
 constexpr int kMaxSrcWidth = 8;   // 2 (p + 1) for p = 3
 constexpr int kNumFaceCoef = 10;  // per face node, see FaceCoef
@@ -29,7 +29,7 @@ struct Closure {
   double alpha[10] = {};  // interior D+ stencil alpha_{-r..q} (Table tab:upwind)
 };
 
-// Builds the closure for orders 2 to 6; returns false on failure (message
+// Builds the closure for orders 2 to 7; returns false on failure (message
 // in *err).
 bool build_closure(int order, Closure* out, const char** err);
 

@@ -57,6 +57,11 @@ struct Stencil<6> {
   static constexpr int R = 2, Q = 4, M = 6;
   static constexpr double a[7] = {1.0 / 30, -2.0 / 5, -7.0 / 12, 4.0 / 3, -1.0 / 2, 2.0 / 15, -1.0 / 60};
 };
+template <>
+struct Stencil<7> {
+  static constexpr int R = 3, Q = 4, M = 7;
+  static constexpr double a[8] = {-1.0 / 105, 1.0 / 10, -3.0 / 5, -1.0 / 4, 1.0, -3.0 / 10, 1.0 / 15, -1.0 / 140};
+};
 
 // ---------------------------------------------------------------------------
 // element `off` of the field starting at the uniform address `base`: the byte
@@ -1142,9 +1147,10 @@ __global__ void energy_kernel(EnergyArgs<T> E) {
 
 // ---------------------------------------------------------------------------
 // launchers
+// 16-row tiles, and order 7 (its s-flux ring), exceed the LDS in double
 template <typename T, int ORDER, int TY>
 static hipError_t launch_stage_t(const StageArgs<T>& a, hipStream_t st) {
-  if constexpr (sizeof(T) == 8 && TY == 16) {
+  if constexpr (sizeof(T) == 8 && (TY == 16 || ORDER == 7)) {
     return hipErrorInvalidValue;
   } else {
     const int nb = ((a.ntiles + 7) / 8) * 8;
@@ -1166,12 +1172,14 @@ hipError_t launch_stage(int order, int ty, const StageArgs<T>& a, hipStream_t st
     if (order == 4) return launch_stage_t<T, 4, 16>(a, st);
     if (order == 5) return launch_stage_t<T, 5, 16>(a, st);
     if (order == 6) return launch_stage_t<T, 6, 16>(a, st);
+    if (order == 7) return launch_stage_t<T, 7, 16>(a, st);
   } else {
     if (order == 2) return launch_stage_t<T, 2, 8>(a, st);
     if (order == 3) return launch_stage_t<T, 3, 8>(a, st);
     if (order == 4) return launch_stage_t<T, 4, 8>(a, st);
     if (order == 5) return launch_stage_t<T, 5, 8>(a, st);
     if (order == 6) return launch_stage_t<T, 6, 8>(a, st);
+    if (order == 7) return launch_stage_t<T, 7, 8>(a, st);
   }
   return hipErrorInvalidValue;
 }
@@ -1198,6 +1206,8 @@ hipError_t launch_edge(int order, const StageArgs<T>& a, hipStream_t st) {
     hipLaunchKernelGGL((edge_kernel<T, 5, KZ>), dim3(nb), dim3(64, KZ), 0, st, a);
   else if (order == 6)
     hipLaunchKernelGGL((edge_kernel<T, 6, KZ>), dim3(nb), dim3(64, KZ), 0, st, a);
+  else if (order == 7)
+    hipLaunchKernelGGL((edge_kernel<T, 7, KZ>), dim3(nb), dim3(64, KZ), 0, st, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1205,7 +1215,7 @@ hipError_t launch_edge(int order, const StageArgs<T>& a, hipStream_t st) {
 
 template <typename T, int ORDER, int TY>
 static hipError_t launch_stage_batch_t(const BatchArgs<T>& b, bool buf, hipStream_t st) {
-  if constexpr (sizeof(T) == 8 && TY == 16) {
+  if constexpr (sizeof(T) == 8 && (TY == 16 || ORDER == 7)) {
     return hipErrorInvalidValue;
   } else {
     const int nb = ((b.total + 7) / 8) * 8;
@@ -1226,12 +1236,14 @@ hipError_t launch_stage_batch(int order, int ty, const BatchArgs<T>& b, bool buf
     if (order == 4) return launch_stage_batch_t<T, 4, 16>(b, buf, st);
     if (order == 5) return launch_stage_batch_t<T, 5, 16>(b, buf, st);
     if (order == 6) return launch_stage_batch_t<T, 6, 16>(b, buf, st);
+    if (order == 7) return launch_stage_batch_t<T, 7, 16>(b, buf, st);
   } else {
     if (order == 2) return launch_stage_batch_t<T, 2, 8>(b, buf, st);
     if (order == 3) return launch_stage_batch_t<T, 3, 8>(b, buf, st);
     if (order == 4) return launch_stage_batch_t<T, 4, 8>(b, buf, st);
     if (order == 5) return launch_stage_batch_t<T, 5, 8>(b, buf, st);
     if (order == 6) return launch_stage_batch_t<T, 6, 8>(b, buf, st);
+    if (order == 7) return launch_stage_batch_t<T, 7, 8>(b, buf, st);
   }
   return hipErrorInvalidValue;
 }
@@ -1250,6 +1262,8 @@ hipError_t launch_edge_batch(int order, const BatchArgs<T>& b, hipStream_t st) {
     hipLaunchKernelGGL((edge_kernel_batch<T, 5, KZ>), dim3(b.total), dim3(64, KZ), 0, st, b);
   else if (order == 6)
     hipLaunchKernelGGL((edge_kernel_batch<T, 6, KZ>), dim3(b.total), dim3(64, KZ), 0, st, b);
+  else if (order == 7)
+    hipLaunchKernelGGL((edge_kernel_batch<T, 7, KZ>), dim3(b.total), dim3(64, KZ), 0, st, b);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
