@@ -13,10 +13,15 @@ from paper_2011_02600_amd import sbp
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared_functions():
-    txt = open(os.path.join(ROOT, "include", "sbp.h")).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(sbp_[a-z_]+)\s*\(", txt)))
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
+
+
+def declared_functions(path=None):
+    names = set()
+    for h in ([path] if path else HEADERS):
+        txt = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(sbp_[a-z_]+)\s*\(", txt))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
@@ -64,9 +69,10 @@ def test_init_rejects_bad_arguments_before_device_use():
     assert "gamma" in sbp.lib().sbp_last_error().decode() or True
 
 
-def test_header_documents_every_entry_point():
-    txt = open(os.path.join(ROOT, "include", "sbp.h")).read()
-    for n in declared_functions():
+@pytest.mark.parametrize("header", HEADERS)
+def test_header_documents_every_entry_point(header):
+    txt = open(header).read()
+    for n in declared_functions(header):
         i = re.search(r"^[a-z].*\b%s\(" % n, txt, re.M).start()  # the declaration's line
         # a comment ends right above it, or above the declarations grouped
         # with it (lines directly before it that are code)
