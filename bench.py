@@ -21,6 +21,11 @@ cpu_baseline times the CPU oracle on a bounded sample of the same workload.
 of uneven size, orders 4 and 6, one sbp_step_batch call): shots per second
 for `steps` steps per shot, beside the same shots stepped one after another.
 
+`--workload surrogate` trains the spectral neural operator on solver-made
+seismograms (64^3 Gaussian-random-field media, 64 receivers x 512 samples)
+and reports its speedup over the solver on held-out media, with the
+fallback to the solver for media outside its calibrated error budget.
+
 `--workload adjoint` measures the material gradient (sbp_gradient): the
 topo_layer block at 129^3, order 6, FP32, a model and a target model with 5 %
 smooth perturbations of rho, lambda and mu, 64 receivers, 1500 steps with a
@@ -183,6 +188,80 @@ def run_adjoint(args, W, sbp, torch, np, dev):
     print(json.dumps(out), flush=True)
 
 
+def run_surrogate(args, W, sbp, torch, np, dev):
+    """Learned surrogate: solver-made training data, GPU training, held-out
+    evaluation with fallback; value = speedup of surrogate + fallback over
+    the solver alone on the held-out media."""
+    from paper_2011_02600_amd import nn
+    from paper_2011_02600_amd import surrogate as SG
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
+    case = W.surrogate_case(T=args.sur_T, amp=args.sur_amp)
+    ntr, nte = args.sur_train, args.sur_test
+    nval = max(1, ntr // 10)
+    log("surrogate: generating %d media" % (ntr + nte))
+    fields = W.surrogate_fields(case, ntr + nte, seed=0)
+    log("surrogate: solving %d shots" % (ntr + nte))
+    y, gen_s = SG.solve_batch(sbp, torch, case, fields, dev, log=log)
+    d = torch.tensor(np.stack(fields), dtype=torch.float32, device=dev)
+    sur = SG.Surrogate(nn, torch, case, dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = sur.train(d[:ntr - nval], y[:ntr - nval], epochs=args.sur_epochs, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    val_err, _ = sur.calibrate(d[ntr - nval:ntr], y[ntr - nval:ntr])
+    # held-out media: the solver alone, then the surrogate (timed separately)
+    log("surrogate: held-out solver run")
+    y_test, solver_s = SG.solve_batch(sbp, torch, case, fields[ntr:], dev, log=log)
+    dt_ = d[ntr:].contiguous()
+    sur.predict(dt_[:8])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = sur.predict(dt_)
+    torch.cuda.synchronize()
+    infer_s = time.perf_counter() - t0
+    err = SG.Surrogate.rel_err(pred, y_test)
+    err_mean_trace = SG.Surrogate.rel_err(sur.ymean.expand_as(y_test), y_test)
+    acc = sur.score(dt_) <= sur.tau
+    mixed_s = infer_s + solver_s * float(np.mean(~acc))
+    out = {
+        "metric": "speedup over the solver (surrogate with fallback, held-out media, <= 5 %% relative L2 "
+                  "trace error on the accepted ones)",
+        "value": round(solver_s / mixed_s, 3),
+        "unit": "x",
+        "n_gpus": 1,
+        "steps": case["T"],
+        "warmup": 1,
+        "ms_per_step": round(1e3 * mixed_s / case["T"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 (network GEMMs, fp32 accumulation) / f32 (solver)",
+        "data": "synthetic",
+        "config": {"workload": "surrogate: %d^3 cube, order-%d FP32 solver, media = half-space x (1 + d), d a "
+                               "Gaussian random field (correlation %d cells, max |d| = %g) on cp and cs, Ricker "
+                               "source, %d receivers x %d samples of v_z; spectral operator (4 cosine-spectral "
+                               "layers, width 32, 8^3 modes)" % (case["n"], case["order"], case["corr_cells"],
+                                                                 case["amp"], len(case["receivers"]), case["T"]),
+                   "train": ntr - nval, "calibration": nval, "test": nte, "epochs": args.sur_epochs},
+        "solver_s_per_shot": round(solver_s / nte, 5),
+        "surrogate_s_per_shot": round(infer_s / nte, 6),
+        "surrogate_only_speedup": round(solver_s / infer_s, 2),
+        "test_rel_l2": {"mean": float(np.mean(err)), "median": float(np.median(err)),
+                        "p95": float(np.quantile(err, 0.95)), "max": float(np.max(err))},
+        "calibration_rel_l2_mean": float(np.mean(val_err)),
+        "mean_trace_rel_l2_mean": float(np.mean(err_mean_trace)),
+        "fallback": {"score": "RMS of d", "threshold": None if not np.isfinite(sur.tau) else float(sur.tau),
+                     "accepted": int(acc.sum()), "rejected": int((~acc).sum()),
+                     "accepted_rel_l2_max": float(np.max(err[acc])) if acc.any() else None,
+                     "accepted_within_5pct": float(np.mean(err[acc] <= 0.05)) if acc.any() else None},
+        "train_s": round(train_s, 2),
+        "data_generation_s": round(gen_s, 2),
+        "final_train_loss": hist[-1] if hist else None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_batched(args, W, sbp, torch, np, dev):
     steps = args.steps if args.steps != 2000 else 100
     warm = args.warmup if args.warmup != 20 else 5
@@ -269,7 +348,12 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--order", type=int, default=6, choices=[2, 3, 4, 5, 6, 7],
                     help="interior order of the topo_layer run (the headline workload is order 6)")
-    ap.add_argument("--workload", default="topo_layer", choices=["topo_layer", "batched", "adjoint"])
+    ap.add_argument("--workload", default="topo_layer", choices=["topo_layer", "batched", "adjoint", "surrogate"])
+    ap.add_argument("--sur-train", type=int, default=2000, help="solver-made training media (surrogate workload)")
+    ap.add_argument("--sur-test", type=int, default=200, help="held-out media (surrogate workload)")
+    ap.add_argument("--sur-epochs", type=int, default=20, help="training epochs (surrogate workload)")
+    ap.add_argument("--sur-T", type=int, default=512, help="time samples per trace (surrogate workload)")
+    ap.add_argument("--sur-amp", type=float, default=0.02, help="max |d| of the media (surrogate workload)")
     ap.add_argument("--adjoint-steps", type=int, default=1500, help="steps of the adjoint workload")
     ap.add_argument("--every", type=int, default=100, help="checkpoint interval of the adjoint workload")
     ap.add_argument("--warmup-grad", type=int, default=1, help="untimed short gradient runs (adjoint workload)")
@@ -303,6 +387,9 @@ def main():
         return
     if args.workload == "adjoint":
         run_adjoint(args, W, sbp, torch, np, dev)
+        return
+    if args.workload == "surrogate":
+        run_surrogate(args, W, sbp, torch, np, dev)
         return
     print("bench: generating workload", file=sys.stderr, flush=True)
     # the interior symbols of orders 2 and 4 reach larger magnitudes than

@@ -6,7 +6,7 @@ GPU kernels against.  Not part of the paper's method.
     h0 = w_lift x + b_lift
     z_l = T^T(R_l T(h_l)) + W_l h_l + b_l,   h_{l+1} = gelu(z_l)  (l < L-1),
                                              h_L = z_{L-1}
-    y[s, r, t] = sum_c h_L[s, c, pos_r] D[c, t] + b_out[r, t]
+    y[s, r, t] = sum_c h_L[s, c, pos_r] D[r, c, t] + b_out[r, t]
 
 T: the m^3 lowest modes of the orthonormal cosine basis
 B[i, k] = sqrt((2 - [k = 0]) / n) cos(pi k (i + 1/2) / n) along each axis;
@@ -51,7 +51,7 @@ def init_params(n, m, C, L, R, Tn, seed=0):
         p["R%d" % l] = rng.standard_normal((m ** 3, C, C)) / C
         p["W%d" % l] = rng.standard_normal((C, C)) / np.sqrt(C)
         p["b%d" % l] = 0.1 * rng.standard_normal(C)
-    p["D"] = rng.standard_normal((C, Tn)) / np.sqrt(C)
+    p["D"] = rng.standard_normal((R, C, Tn)) / np.sqrt(C)
     p["b_out"] = 0.1 * rng.standard_normal((R, Tn))
     return p
 
@@ -74,7 +74,7 @@ def forward(p, x, pos, m, L):
         zs.append(z)
         hs.append(h)
     f = h.reshape(S, C, -1)[:, :, pos].transpose(0, 2, 1)  # (S, R, C)
-    y = f @ p["D"] + p["b_out"][None]
+    y = np.einsum("src,rct->srt", f, p["D"]) + p["b_out"][None]
     return y, dict(x=x, hs=hs, zs=zs, xhs=xhs, f=f, B=B, m=m, L=L, pos=pos)
 
 
@@ -84,9 +84,9 @@ def backward(p, dy, cache):
     S, n = x.shape[0], x.shape[1]
     C = p["w_lift"].shape[0]
     g = {}
-    g["D"] = np.einsum("src,srt->ct", f, dy)
+    g["D"] = np.einsum("src,srt->rct", f, dy)
     g["b_out"] = dy.sum(axis=0)
-    df = dy @ p["D"].T  # (S, R, C)
+    df = np.einsum("srt,rct->src", dy, p["D"])  # (S, R, C)
     dh = np.zeros_like(hs[-1]).reshape(S, C, -1)
     for r, q in enumerate(pos):
         dh[:, :, q] += df[:, r, :]

@@ -204,6 +204,23 @@ void layout(sbp_ctx* h) {
 int copy_in(sbp_ctx* h, char* dst, const void* src, int nf, hipMemcpyKind kind) {
   const Geometry& g = h->g;
   const std::size_t es = h->esize, rows = (std::size_t)g.nr * g.ns;
+  if (kind == hipMemcpyHostToDevice) {
+    // from pageable host memory: lay the fields out on the host and copy them
+    // in one piece (a 2D copy from pageable memory moves row by row)
+    std::vector<char> tmp((std::size_t)nf * h->field * es, 0);
+    for (int f = 0; f < nf; ++f) {
+      char* d = tmp.data() + (std::size_t)f * h->field * es;
+      const char* sf = (const char*)src + (std::size_t)f * g.n * es;
+      for (std::size_t r = 0; r < rows; ++r) {
+        const char* sr = sf + r * g.nq * es;
+        std::memcpy(d + r * h->px * es, sr, (g.nq - 1) * es);
+        std::memcpy(d + ((std::size_t)h->nm.cbase + r) * es, sr + (g.nq - 1) * es, es);
+      }
+    }
+    HIPCHK(hipMemcpyAsync(dst, tmp.data(), tmp.size(), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return SBP_OK;
+  }
   for (int f = 0; f < nf; ++f) {
     char* d = dst + (std::size_t)f * h->field * es;
     const char* s = (const char*)src + (std::size_t)f * g.n * es;

@@ -10,7 +10,7 @@ place of the Fourier basis, so that all transforms are real GEMMs):
     h0 = w_lift x + b_lift                               (1 -> C channels)
     h_{l+1} = act(T^T(R_l T(h_l)) + W_l h_l + b_l)       l = 0..L-1 (act: GELU,
                                                          none on the last layer)
-    traces[r, t] = sum_c h_L[c, pos_r] D[c, t] + b_out[r, t]
+    traces[r, t] = sum_c h_L[c, pos_r] D[r, c, t] + b_out[r, t]
 
 T maps a grid function on n^3 points to its m^3 lowest cosine modes
 (B^T along each axis, B[i, k] = sqrt((2 - [k = 0]) / n) cos(pi k (i + 1/2) / n)),
@@ -111,7 +111,7 @@ class SpectralOperator:
             p["R%d" % l] = f32(rng.standard_normal((m3, C, C)) / C)
             p["W%d" % l] = f32(rng.standard_normal((C, C)) / math.sqrt(C))
             p["b%d" % l] = f32(np.zeros(C))
-        p["D"] = f32(rng.standard_normal((C, T)) / math.sqrt(C))
+        p["D"] = f32(rng.standard_normal((self.R, C, T)) / math.sqrt(C))
         p["b_out"] = f32(np.zeros((self.R, T)))
         self.params = p
         self.grads = {k: torch.zeros_like(v) for k, v in p.items()}
@@ -192,7 +192,9 @@ class SpectralOperator:
         f = self._buf("feat", (S, self.R, C))
         _ck(lb.sbp_nn_gather(S, C, P, self.R, _p(self.pos), _p(h), _p(f), st))
         y = self._buf("y", (S, self.R, self.T))
-        gemm(f, p["D"], y, S * self.R, self.T, C, (0, C, 1), (0, self.T, 1), (0, self.T, 1), stream=st)
+        R, T = self.R, self.T
+        # per receiver r: y[:, r, :] (S x T) = f[:, r, :] (S x C) @ D[r] (C x T)
+        gemm(f, p["D"], y, S, T, C, (C, R * C, 1), (C * T, T, 1), (T, R * T, 1), batch=R, stream=st)
         _ck(lb.sbp_nn_add_rows(S, self.R * self.T, _p(p["b_out"]), _p(y), st))
         return y
 
@@ -212,10 +214,10 @@ class SpectralOperator:
         p, g, st, lb = self.params, self.grads, self.stream, lib()
         # head: y = F D + b_out
         f = self._bufs["feat"]
-        gemm(f, dy, g["D"], C, T, S * R, (0, 1, C), (0, T, 1), (0, T, 1), stream=st)
+        gemm(f, dy, g["D"], C, T, S, (C, 1, R * C), (T, R * T, 1), (C * T, T, 1), batch=R, stream=st)
         _ck(lb.sbp_nn_sum_rows(S, R * T, _p(dy), _p(g["b_out"]), 0, st))
         df = self._buf("dfeat", (S, R, C))
-        gemm(dy, p["D"], df, S * R, C, T, (0, T, 1), (0, 1, T), (0, C, 1), stream=st)
+        gemm(dy, p["D"], df, S, C, T, (T, R * T, 1), (C * T, 1, T), (C, R * C, 1), batch=R, stream=st)
         dh = self._buf("dh", (S, C, P))
         dh.zero_()
         _ck(lb.sbp_nn_scatter(S, C, P, R, _p(self.pos), _p(df), _p(dh), st))

@@ -115,3 +115,35 @@ def test_training_steps_reduce_the_loss():
         losses.append(loss)
     say("  loss %.4f -> %.4f" % (losses[0], losses[-1]))
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_surrogate_pipeline_gains_over_the_mean_trace_and_the_solver():
+    """End to end at a small size: solver-made training data (batched
+    shots), GPU training, held-out evaluation.  The trained network must beat
+    the method without it -- the mean training trace as the prediction --
+    by a wide margin, and answer faster than the solver."""
+    say("case: surrogate pipeline 16^3, 128 training / 16 held-out shots")
+    import time
+    import workloads as W
+    from paper_2011_02600_amd import nn, sbp
+    from paper_2011_02600_amd import surrogate as SG
+    dev = torch.device("cuda:0")
+    case = W.surrogate_case(n=16, T=96, amp=0.01, corr_cells=4, nrec_side=4)
+    fields = W.surrogate_fields(case, 144, seed=3)
+    y, _ = SG.solve_batch(sbp, torch, case, fields, dev)
+    d = torch.tensor(np.stack(fields), dtype=torch.float32, device=dev)
+    sur = SG.Surrogate(nn, torch, case, dev, modes=4, width=16)
+    hist = sur.train(d[:128], y[:128], epochs=15, lr=3e-3)
+    pred = sur.predict(d[128:])
+    err = SG.Surrogate.rel_err(pred, y[128:])
+    base = SG.Surrogate.rel_err(sur.ymean.expand_as(y[128:]), y[128:])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sur.predict(d[128:])
+    torch.cuda.synchronize()
+    t_net = time.perf_counter() - t0
+    _, t_solver = SG.solve_batch(sbp, torch, case, fields[128:], dev)
+    say("  loss %.2f -> %.2f; held-out rel L2 %.3f (mean trace %.3f); network %.4f s, solver %.4f s"
+        % (hist[0], hist[-1], float(np.mean(err)), float(np.mean(base)), t_net, t_solver))
+    assert np.mean(err) < 0.5 * np.mean(base)
+    assert t_net < t_solver

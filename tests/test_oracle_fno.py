@@ -33,7 +33,7 @@ def test_basis_orthonormal_and_projection():
 def test_backward_matches_finite_differences(L):
     p, x, pos, m, L = small(L=L)
     rng = np.random.default_rng(7)
-    target = rng.standard_normal((x.shape[0], len(pos), p["D"].shape[1]))
+    target = rng.standard_normal((x.shape[0], len(pos), p["D"].shape[2]))
 
     def loss(pp, xx):
         y, _ = fno.forward(pp, xx, pos, m, L)

@@ -259,3 +259,30 @@ def adjoint_case(n=129, seed=0, amp=0.05, corr_cells=10, cfl=0.5, nrec_side=8):
     target = perturbed(1000 * seed + 21)
     wl.update(model=model, target=target, dt=cfl_dt(wl["xyz"], np.maximum(model[1], target[1]), cfl))
     return wl
+
+
+def surrogate_case(n=64, h=0.05, T=512, amp=0.02, corr_cells=16, f0=6.0, cfl=0.5, nrec_side=8, order=4):
+    """Fixed geometry of the surrogate workload: an n^3 cube with spacing h
+    (km), half-space background (cs 3.464, cp 6.0, rho 2.7), free surface on
+    top and absorbing elsewhere, a Ricker moment source (M = sxy, f0) at
+    reference point (0.5, 0.5, 0.4), nrec_side^2 receivers on the top face,
+    T steps at the dt of CFL `cfl` for the fastest medium the perturbations
+    allow (cp (1 + amp)).  Perturbations come from surrogate_fields."""
+    xyz = unit_cube(n, n, n) * (h * (n - 1))
+    shape = (n, n, n)
+    cp = np.full(shape, 6.0)
+    cs = np.full(shape, 3.464)
+    rho = np.full(shape, 2.7)
+    step = (n - 1) / nrec_side
+    rec = [(int(round(step * (a + 0.5))), int(round(step * (b + 0.5))), n - 1)
+           for b in range(nrec_side) for a in range(nrec_side)]
+    return dict(n=n, xyz=xyz, rho=rho, cp=cp, cs=cs, order=order, gamma=(0.0, 0.0, 0.0, 0.0, 0.0, 1.0),
+                dt=cfl_dt(xyz, cp * (1 + amp), cfl), T=T, amp=amp, corr_cells=corr_cells,
+                src_xi=(0.5, 0.5, 0.4), src_M=(0.0, 0.0, 0.0, 1.0, 0.0, 0.0), src_f0=f0, src_t0=1.2 / f0,
+                receivers=np.array(rec, dtype=np.int32))
+
+
+def surrogate_fields(case, count, seed):
+    """`count` seeded perturbation fields d (grf, max |d| = amp each)."""
+    n = case["n"]
+    return [grf((n, n, n), case["corr_cells"], 100000 * seed + i, case["amp"]) for i in range(count)]
