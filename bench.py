@@ -351,7 +351,7 @@ def main():
     ap.add_argument("--workload", default="topo_layer", choices=["topo_layer", "batched", "adjoint", "surrogate"])
     ap.add_argument("--sur-train", type=int, default=2000, help="solver-made training media (surrogate workload)")
     ap.add_argument("--sur-test", type=int, default=200, help="held-out media (surrogate workload)")
-    ap.add_argument("--sur-epochs", type=int, default=20, help="training epochs (surrogate workload)")
+    ap.add_argument("--sur-epochs", type=int, default=30, help="training epochs (surrogate workload)")
     ap.add_argument("--sur-T", type=int, default=512, help="time samples per trace (surrogate workload)")
     ap.add_argument("--sur-amp", type=float, default=0.02, help="max |d| of the media (surrogate workload)")
     ap.add_argument("--adjoint-steps", type=int, default=1500, help="steps of the adjoint workload")
