@@ -26,6 +26,9 @@ seismograms (64^3 Gaussian-random-field media, 64 receivers x 512 samples)
 and reports its speedup over the solver on held-out media, with the
 fallback to the solver for media outside its calibrated error budget.
 
+`--workload orders` compares the interior orders 2-7 at marginal resolution
+on the topography workload against a 2x refined order-6 reference.
+
 `--workload adjoint` measures the material gradient (sbp_gradient): the
 topo_layer block at 129^3, order 6, FP32, a model and a target model with 5 %
 smooth perturbations of rho, lambda and mu, 64 receivers, 1500 steps with a
@@ -262,6 +265,66 @@ def run_surrogate(args, W, sbp, torch, np, dev):
     print(json.dumps(out), flush=True)
 
 
+def run_orders(args, W, sbp, torch, np, dev):
+    """Odd and even interior orders at marginal resolution on synthetic
+    topography: the topo_layer workload on a coarse 129 x 129 x 97 grid (ten
+    points per wavelength of the 2 Hz Ricker peak in the soft layer, four at
+    2.5 f0) at CFL 0.25 (stable for every order) for every order the library
+    runs, against order 6 on the 2x refined grid (257 x 257 x 193, half the
+    time step, same receivers).  Reports the relative L2 error of the
+    receiver traces per order."""
+    log = lambda msg: print(msg, file=sys.stderr, flush=True)
+    coarse = W.topo_layer(nq=129, nr=129, ns=97, nrec_side=8, cfl=0.25)
+    fine = W.topo_layer(nq=257, nr=257, ns=193, nrec_side=8)
+    assert np.array_equal(fine["receivers"][:, :2], 2 * coarse["receivers"][:, :2])
+    dt = coarse["dt"]
+    tend = args.orders_time
+    nc = int(round(tend / dt))
+
+    def traces(wl, order, dtt, nsteps):
+        s = sbp.Solver(wl["xyz"], order=order, dtype="f32", gamma=wl["gamma"], device=dev)
+        s.set_material(wl["rho"], wl["cp"], wl["cs"])
+        s.add_source(wl["src_xi"], wl["src_M"], sbp.SBP_STF_RICKER, wl["src_f0"], wl["src_t0"])
+        tr = s.record(wl["receivers"], nsteps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.step(nsteps, dtt)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out = tr.double().cpu().numpy()
+        s.close()
+        return out, el
+
+    log("orders: reference, order 6 on 257 x 257 x 193, %d steps" % (2 * nc))
+    ref, _ = traces(fine, 6, dt / 2, 2 * nc)
+    ref = ref[1::2]  # the fine steps that end at the coarse times
+    res = {}
+    for order in (2, 3, 4, 5, 6, 7):
+        tr, el = traces(coarse, order, dt, nc)
+        err = float(np.linalg.norm(tr - ref) / np.linalg.norm(ref))
+        res[str(order)] = {"rel_l2": round(err, 5), "s": round(el, 3)}
+        log("orders: order %d: relative L2 trace error %.4f (%.2f s)" % (order, err, el))
+    out = {
+        "metric": "relative L2 receiver-trace error at marginal resolution per interior order (lower is better)",
+        "value": res["6"]["rel_l2"],
+        "unit": "relative L2",
+        "n_gpus": 1,
+        "steps": nc,
+        "warmup": 0,
+        "ms_per_step": None,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "odd/even orders: topo_layer on 129 x 129 x 97 (h = 100 m horizontally), 2 Hz "
+                               "Ricker, 64 surface receivers, %.1f s, CFL 0.25; reference order 6 on "
+                               "257 x 257 x 193 with dt/2" % tend, "dt": dt},
+        "per_order": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_batched(args, W, sbp, torch, np, dev):
     steps = args.steps if args.steps != 2000 else 100
     warm = args.warmup if args.warmup != 20 else 5
@@ -348,7 +411,9 @@ def main():
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--order", type=int, default=6, choices=[2, 3, 4, 5, 6, 7],
                     help="interior order of the topo_layer run (the headline workload is order 6)")
-    ap.add_argument("--workload", default="topo_layer", choices=["topo_layer", "batched", "adjoint", "surrogate"])
+    ap.add_argument("--workload", default="topo_layer",
+                    choices=["topo_layer", "batched", "adjoint", "surrogate", "orders"])
+    ap.add_argument("--orders-time", type=float, default=6.0, help="simulated seconds (orders workload)")
     ap.add_argument("--sur-train", type=int, default=2000, help="solver-made training media (surrogate workload)")
     ap.add_argument("--sur-test", type=int, default=200, help="held-out media (surrogate workload)")
     ap.add_argument("--sur-epochs", type=int, default=30, help="training epochs (surrogate workload)")
@@ -390,6 +455,9 @@ def main():
         return
     if args.workload == "surrogate":
         run_surrogate(args, W, sbp, torch, np, dev)
+        return
+    if args.workload == "orders":
+        run_orders(args, W, sbp, torch, np, dev)
         return
     print("bench: generating workload", file=sys.stderr, flush=True)
     # the interior symbols of orders 2 and 4 reach larger magnitudes than
