@@ -158,6 +158,20 @@ def run_adjoint(args, W, sbp, torch, np, dev):
     g = grad.double()
     if not bool(torch.isfinite(g).all()):
         raise RuntimeError("non-finite gradient")
+    # the autograd path: a checkpointed forward run, then the reverse sweep alone
+    s.set_state(Q0, 0.0)
+    s.record(wl["receivers"], steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step_checkpointed(steps, dt, every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    grad2 = s.gradient_from_checkpoints(res)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fwd_ck_s, rev_s = t1 - t0, t2 - t1
+    if not torch.equal(grad2, grad):
+        raise RuntimeError("gradient from checkpoints differs from sbp_gradient")
     nbytes = sbp.sbp_adjoint_bytes(s.h, steps, every)
     print("bench: gradient of %d steps in %.3f s, forward %.3f s" % (steps, grad_s, fwd_s), file=sys.stderr,
           flush=True)
@@ -185,6 +199,8 @@ def run_adjoint(args, W, sbp, torch, np, dev):
         "gradient_s": round(grad_s, 4),
         "forward_s": round(fwd_s, 4),
         "gradient_over_forward": round(grad_s / fwd_s, 3),
+        "autograd_path": {"forward_checkpointed_s": round(fwd_ck_s, 4), "reverse_from_checkpoints_s": round(rev_s, 4),
+                          "forward_plus_backward_over_forward": round((fwd_ck_s + rev_s) / fwd_s, 3)},
         "misfit": misfit,
         "grad_max_abs": [float(g[i].abs().max()) for i in range(3)],
     }

@@ -240,6 +240,28 @@ int sbp_gradient(sbp_handle h, int nsteps, double dt, const void* residual_devic
                  size_t adj_bytes, void* grad_device, void* qbar_device);
 
 /*
+ * sbp_step (sources, receivers recorded) that also keeps the checkpoints a
+ * later sbp_gradient_from_checkpoints needs, in adj_ws (the layout and size of
+ * sbp_adjoint_bytes(h, nsteps, every, .)); for a forward pass whose gradient
+ * may be wanted afterwards (the backward pass then skips the forward run).
+ * Synchronises nothing; the checkpoints stay valid until the handle is
+ * stepped again or its state, medium or sources change.
+ */
+int sbp_step_checkpointed(sbp_handle h, int nsteps, double dt, int every, void* adj_ws, size_t adj_bytes);
+
+/*
+ * The gradient of sbp_gradient for the run of the last sbp_step_checkpointed
+ * on this handle (its nsteps, dt and every; adj_ws the same workspace), the
+ * handle standing at the end of that run: only the reverse sweep.  Results
+ * are those of sbp_gradient from the run's initial state.  SBP_ESTATE if
+ * there are no such checkpoints.  Leaves the state and the checkpoints as
+ * they are (so several residuals can be differentiated).  Synchronises the
+ * stream.
+ */
+int sbp_gradient_from_checkpoints(sbp_handle h, const void* residual_device, void* adj_ws, size_t adj_bytes,
+                                  void* grad_device, void* qbar_device);
+
+/*
  * Discrete energy 1/2 <Q, P~^{-1} Q>_H = 1/2 sum H_ijk J (rho |v|^2 +
  * sigma^T C^{-1} sigma) of the current state (eq. physical_energy_discrete
  * with the curvilinear weight J), accumulated in double.  Synchronises the

@@ -1,9 +1,12 @@
 """torch.autograd interface of the solver: receiver traces as a
 differentiable function of the nodal material (rho, lambda, mu).
 
-The forward pass steps the solver (sbp_step with receivers); the backward
-pass calls sbp_gradient, the library's discrete adjoint, with the incoming
-gradient of the traces as the residual.  Argument marshalling only: all
+The forward pass steps the solver keeping checkpoints
+(sbp_step_checkpointed, receivers recorded); the backward pass runs the
+library's discrete adjoint from those checkpoints
+(sbp_gradient_from_checkpoints) with the incoming gradient of the traces as
+the residual, or, if the solver was used in between, sbp_gradient from the
+saved initial state.  Argument marshalling only: all
 arithmetic of both passes runs in the HIP library.
 """
 import numpy as np
@@ -28,7 +31,7 @@ class Seismograms(torch.autograd.Function):
         solver.set_material(*_cp_cs(rho, lam, mu))
         solver.set_state(Q0, 0.0)
         traces = solver.record(receivers, nsteps)
-        solver.step(nsteps, dt)
+        solver.step_checkpointed(nsteps, dt, every)
         ctx.solver, ctx.Q0, ctx.receivers = solver, Q0, receivers
         ctx.nsteps, ctx.dt, ctx.every = nsteps, dt, every
         ctx.mat = (rho, lam, mu)
@@ -36,11 +39,18 @@ class Seismograms(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_traces):
+        from .sbp import SBPError, SBP_ESTATE
         s = ctx.solver
-        s.set_material(*_cp_cs(*ctx.mat))
-        s.set_state(ctx.Q0, 0.0)
-        s.record(ctx.receivers, ctx.nsteps)
-        g = s.gradient(ctx.nsteps, ctx.dt, grad_traces, ctx.every)
+        try:
+            # the forward run's checkpoints, if the solver was not used since
+            g = s.gradient_from_checkpoints(grad_traces)
+        except SBPError as e:
+            if e.code != SBP_ESTATE:
+                raise
+            s.set_material(*_cp_cs(*ctx.mat))
+            s.set_state(ctx.Q0, 0.0)
+            s.record(ctx.receivers, ctx.nsteps)
+            g = s.gradient(ctx.nsteps, ctx.dt, grad_traces, ctx.every)
         dev = ctx.mat[0].device
         out = [g[i].to(device=dev, dtype=ctx.mat[i].dtype) for i in range(3)]
         return out[0], out[1], out[2], None, None, None, None, None, None

@@ -113,6 +113,13 @@ struct sbp_ctx {
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   double prof_stage_ms = 0.0, prof_edge_ms = 0.0;
   long long prof_n = 0;
+  // checkpoints of the last sbp_step_checkpointed (valid until the state,
+  // the medium or the sources change)
+  bool ck_valid = false;
+  const char* ck_ws = nullptr;
+  int ck_nsteps = 0, ck_every = 0;
+  double ck_dt = 0.0, ck_t0 = 0.0;
+  long long ck_steps = 0;
 };
 
 namespace {
@@ -1076,41 +1083,25 @@ int do_adjoint_rhs(sbp_ctx* h, const void* lam, void* out, char* adj) {
   return copy_out(h, out, adj + L.qb, 9, hipMemcpyDeviceToDevice);
 }
 
-// Misfit gradient: a forward run of nsteps from the current state that keeps
-// checkpoints, then the reverse sweep block by block (each block recomputed
-// from its checkpoint, keeping every stage input of the block).
+// Reverse sweep of the misfit gradient over nsteps steps of size dt that
+// started at time t0, from the checkpoints in the adjoint workspace: block by
+// block from the end, each block recomputed from its checkpoint (keeping every
+// stage input of the block), then the reverse stages.
 template <typename T>
-int do_gradient(sbp_ctx* h, int nsteps, double dt, const T* res, int every, char* adj, void* grad_out,
-                void* qbar_out) {
+int adj_reverse(sbp_ctx* h, int nsteps, double dt, double t0, const T* res, const AdjLayout& L, char* adj,
+                void* grad_out, void* qbar_out) {
   int rc = prepare_bounds(h);
   if (rc) return rc;
-  const AdjLayout L = adj_layout(h, nsteps, every);
   const StageArgs<T> base = stage_args<T>(h);
   AdjArgs<T> a = adj_args<T>(h, adj, L);
   const std::size_t F9 = 9 * h->field;
-  T* ck = (T*)(adj + L.ck);
+  const T* ck = (const T*)(adj + L.ck);
   T* blk = (T*)(adj + L.blk);
-  T* st = (T*)(adj + L.st);
-  T* const S[4] = {st, st + F9, st + 2 * F9, st + 3 * F9};
-  T* spare = st + 4 * F9;
+  T* spare = (T*)(adj + L.st) + 4 * F9;
   T* dqs = (T*)(adj + L.dqs);
   T* rbuf = (T*)(adj + L.r);
   T* cu = (T*)(adj + L.cu);
-  T* state = (T*)(h->ws + (h->cur ? h->off_qb : h->off_qa));
-  const double t0 = h->t;
   const std::size_t bytes9 = F9 * sizeof(T);
-
-  // forward pass with checkpoints (ping-pong through the y and r buffers)
-  T* X = a.y;
-  T* Y = rbuf;
-  HIPCHK(hipMemcpyAsync(X, state, bytes9, hipMemcpyDeviceToDevice, h->stream));
-  for (int n = 0; n < nsteps; ++n) {
-    if (n % L.every == 0)
-      HIPCHK(hipMemcpyAsync(ck + (std::size_t)(n / L.every) * F9, X, bytes9, hipMemcpyDeviceToDevice, h->stream));
-    if ((rc = step_explicit<T>(h, base, t0 + n * dt, dt, X, S, Y, dqs))) return rc;
-    std::swap(X, Y);
-  }
-  HIPCHK(hipMemcpyAsync(state, X, bytes9, hipMemcpyDeviceToDevice, h->stream));
 
   // unit material (lambda/J = 0, mu/J = 1, 1/(rho J) = 1), J, zeroed accumulators
   HIPCHK(hipMemcpyAsync(cu, h->ws + h->off_coef, 9 * h->field * sizeof(T), hipMemcpyDeviceToDevice, h->stream));
@@ -1120,13 +1111,11 @@ int do_gradient(sbp_ctx* h, int nsteps, double dt, const T* res, int every, char
     std::vector<T> jt(h->g.n);
     for (std::size_t o = 0; o < h->g.n; ++o) jt[o] = (T)h->J[o];
     if ((rc = copy_in(h, adj + L.jac, jt.data(), 1, hipMemcpyHostToDevice))) return rc;
-    HIPCHK(hipStreamSynchronize(h->stream));
   }
   HIPCHK(launch_fill<T>(a.qb, F9, T(0), h->stream));
   HIPCHK(launch_fill<T>(a.grad, 3 * h->field, T(0), h->stream));
   const long long* roff = (const long long*)(h->ws + h->off_rec);
 
-  // reverse sweep
   for (int c = L.nck - 1; c >= 0; --c) {
     const int n0 = c * L.every, n1 = std::min(nsteps, n0 + L.every);
     // slot n - n0 of the block: the state of step n, then its stage inputs 2-5
@@ -1156,8 +1145,71 @@ int do_gradient(sbp_ctx* h, int nsteps, double dt, const T* res, int every, char
   if ((rc = copy_out(h, grad_out, adj + L.grad, 3, hipMemcpyDeviceToDevice))) return rc;
   if (qbar_out && (rc = copy_out(h, qbar_out, adj + L.qb, 9, hipMemcpyDeviceToDevice))) return rc;
   HIPCHK(hipStreamSynchronize(h->stream));
+  return SBP_OK;
+}
+
+// Misfit gradient: a forward run of nsteps from the current state that keeps
+// checkpoints (receivers not recorded), then the reverse sweep.
+template <typename T>
+int do_gradient(sbp_ctx* h, int nsteps, double dt, const T* res, int every, char* adj, void* grad_out,
+                void* qbar_out) {
+  int rc = prepare_bounds(h);
+  if (rc) return rc;
+  const AdjLayout L = adj_layout(h, nsteps, every);
+  const StageArgs<T> base = stage_args<T>(h);
+  const std::size_t F9 = 9 * h->field;
+  T* ck = (T*)(adj + L.ck);
+  T* st = (T*)(adj + L.st);
+  T* const S[4] = {st, st + F9, st + 2 * F9, st + 3 * F9};
+  T* dqs = (T*)(adj + L.dqs);
+  T* state = (T*)(h->ws + (h->cur ? h->off_qb : h->off_qa));
+  const double t0 = h->t;
+  const std::size_t bytes9 = F9 * sizeof(T);
+  h->ck_valid = false;
+  // forward pass with checkpoints (ping-pong through the y and r buffers)
+  T* X = (T*)(adj + L.y);
+  T* Y = (T*)(adj + L.r);
+  HIPCHK(hipMemcpyAsync(X, state, bytes9, hipMemcpyDeviceToDevice, h->stream));
+  for (int n = 0; n < nsteps; ++n) {
+    if (n % L.every == 0)
+      HIPCHK(hipMemcpyAsync(ck + (std::size_t)(n / L.every) * F9, X, bytes9, hipMemcpyDeviceToDevice, h->stream));
+    if ((rc = step_explicit<T>(h, base, t0 + n * dt, dt, X, S, Y, dqs))) return rc;
+    std::swap(X, Y);
+  }
+  HIPCHK(hipMemcpyAsync(state, X, bytes9, hipMemcpyDeviceToDevice, h->stream));
+  if ((rc = adj_reverse<T>(h, nsteps, dt, t0, res, L, adj, grad_out, qbar_out))) return rc;
   h->t = t0 + nsteps * dt;
   h->steps += nsteps;
+  return SBP_OK;
+}
+
+// sbp_step with checkpoints kept for a later sbp_gradient_from_checkpoints
+template <typename T>
+int do_step_checkpointed(sbp_ctx* h, int nsteps, double dt, int every, char* adj) {
+  const AdjLayout L = adj_layout(h, nsteps, every);
+  const std::size_t F9 = 9 * h->field;
+  const std::size_t bytes9 = F9 * sizeof(T);
+  h->ck_valid = false;
+  const double t0 = h->t;
+  const long long s0 = h->steps;
+  for (int n = 0; n < nsteps; ++n) {
+    if (n % L.every == 0) {
+      const T* state = (const T*)(h->ws + (h->cur ? h->off_qb : h->off_qa));
+      HIPCHK(hipMemcpyAsync(adj + L.ck + (std::size_t)(n / L.every) * bytes9, state, bytes9, hipMemcpyDeviceToDevice,
+                            h->stream));
+    }
+    h->t = t0 + n * dt;  // the stage times of sbp_step(h, nsteps, dt)
+    int rc = do_steps<T>(h, 1, dt);
+    if (rc) return rc;
+  }
+  h->t = t0 + nsteps * dt;
+  h->ck_valid = true;
+  h->ck_ws = adj;
+  h->ck_nsteps = nsteps;
+  h->ck_every = every;
+  h->ck_dt = dt;
+  h->ck_t0 = t0;
+  h->ck_steps = s0 + nsteps;
   return SBP_OK;
 }
 
@@ -1253,6 +1305,7 @@ int sbp_init_grid(sbp_handle* out, int nq, int nr, int ns, const double* xyz, in
 
 int sbp_set_material(sbp_handle h, const double* rho, const double* cp, const double* cs) {
   if (!h || !rho || !cp || !cs) return fail(SBP_EINVAL, "NULL argument");
+  h->ck_valid = false;
   const Geometry& g = h->g;
   const std::size_t n = g.n;
   std::vector<double> lamJ(n), muJ(n), rJ(n);
@@ -1308,6 +1361,7 @@ int sbp_set_material(sbp_handle h, const double* rho, const double* cp, const do
 
 int sbp_add_source(sbp_handle h, const double* xi, const double* M, int stf, double param, double t0) {
   if (!h || !xi || !M) return fail(SBP_EINVAL, "NULL argument");
+  h->ck_valid = false;
   if ((int)h->src.size() >= kMaxSources) return fail(SBP_EINVAL, "at most %d sources", kMaxSources);
   if (stf != SBP_STF_RICKER && stf != SBP_STF_EXPT) return fail(SBP_EINVAL, "unknown source-time function");
   if (!(param > 0)) return fail(SBP_EINVAL, "source parameter must be positive");
@@ -1364,12 +1418,14 @@ int sbp_add_source(sbp_handle h, const double* xi, const double* M, int stf, dou
 
 int sbp_clear_sources(sbp_handle h) {
   if (!h) return fail(SBP_EINVAL, "NULL handle");
+  h->ck_valid = false;
   h->src.clear();
   return SBP_OK;
 }
 
 int sbp_set_state(sbp_handle h, const void* q, int q_is_device, double t) {
   if (!h || !q) return fail(SBP_EINVAL, "NULL argument");
+  h->ck_valid = false;
   char* dst = h->ws + (h->cur ? h->off_qb : h->off_qa);
   int rc = copy_in(h, dst, q, 9, q_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice);
   if (rc) return rc;
@@ -1482,6 +1538,36 @@ int sbp_gradient(sbp_handle h, int nsteps, double dt, const void* residual_devic
                                   qbar_device)
              : do_gradient<double>(h, nsteps, dt, (const double*)residual_device, every, (char*)adj_ws,
                                    grad_device, qbar_device);
+}
+
+int sbp_step_checkpointed(sbp_handle h, int nsteps, double dt, int every, void* adj_ws, size_t adj_bytes) {
+  if (!h) return fail(SBP_EINVAL, "NULL handle");
+  if (!h->have_material) return fail(SBP_ESTATE, "sbp_set_material has not been called");
+  if (nsteps < 1 || every < 1 || !(dt > 0) || !std::isfinite(dt))
+    return fail(SBP_EINVAL, "need nsteps >= 1, every >= 1 and dt > 0");
+  if (h->nrec > 0 && h->rec_step + nsteps > h->rec_max)
+    return fail(SBP_EINVAL, "receiver buffer holds %d steps; %lld recorded, %d requested", h->rec_max,
+                h->rec_step, nsteps);
+  int rc = check_adj_ws(adj_ws, adj_bytes, adj_layout(h, nsteps, every).total);
+  if (rc) return rc;
+  return h->dtype == SBP_F32 ? do_step_checkpointed<float>(h, nsteps, dt, every, (char*)adj_ws)
+                             : do_step_checkpointed<double>(h, nsteps, dt, every, (char*)adj_ws);
+}
+
+int sbp_gradient_from_checkpoints(sbp_handle h, const void* residual_device, void* adj_ws, size_t adj_bytes,
+                                  void* grad_device, void* qbar_device) {
+  if (!h || !residual_device || !grad_device || !adj_ws) return fail(SBP_EINVAL, "NULL argument");
+  if (!h->ck_valid || h->ck_ws != (const char*)adj_ws || h->ck_steps != h->steps)
+    return fail(SBP_ESTATE, "no checkpoints of the current state in this workspace: call sbp_step_checkpointed");
+  if (h->nrec <= 0) return fail(SBP_ESTATE, "no receivers: call sbp_record first");
+  const AdjLayout L = adj_layout(h, h->ck_nsteps, h->ck_every);
+  int rc = check_adj_ws(adj_ws, adj_bytes, L.total);
+  if (rc) return rc;
+  return h->dtype == SBP_F32
+             ? adj_reverse<float>(h, h->ck_nsteps, h->ck_dt, h->ck_t0, (const float*)residual_device, L,
+                                  (char*)adj_ws, grad_device, qbar_device)
+             : adj_reverse<double>(h, h->ck_nsteps, h->ck_dt, h->ck_t0, (const double*)residual_device, L,
+                                   (char*)adj_ws, grad_device, qbar_device);
 }
 
 int sbp_energy(sbp_handle h, double* E) {

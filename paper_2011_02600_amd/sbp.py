@@ -61,6 +61,8 @@ def lib():
             "sbp_adjoint_bytes": [c_void_p, c_int, c_int, P(c_size_t)],
             "sbp_adjoint_rhs": [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t],
             "sbp_gradient": [c_void_p, c_int, c_double, c_void_p, c_int, c_void_p, c_size_t, c_void_p, c_void_p],
+            "sbp_step_checkpointed": [c_void_p, c_int, c_double, c_int, c_void_p, c_size_t],
+            "sbp_gradient_from_checkpoints": [c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, c_void_p],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -206,6 +208,14 @@ def sbp_adjoint_rhs(h, lam_ptr, out_ptr, ws_ptr, ws_bytes):
     _check(lib().sbp_adjoint_rhs(h, lam_ptr, out_ptr, ws_ptr, int(ws_bytes)))
 
 
+def sbp_step_checkpointed(h, nsteps, dt, every, ws_ptr, ws_bytes):
+    _check(lib().sbp_step_checkpointed(h, int(nsteps), float(dt), int(every), ws_ptr, int(ws_bytes)))
+
+
+def sbp_gradient_from_checkpoints(h, res_ptr, ws_ptr, ws_bytes, grad_ptr, qbar_ptr=None):
+    _check(lib().sbp_gradient_from_checkpoints(h, res_ptr, ws_ptr, int(ws_bytes), grad_ptr, qbar_ptr))
+
+
 def sbp_gradient(h, nsteps, dt, res_ptr, every, ws_ptr, ws_bytes, grad_ptr, qbar_ptr=None):
     _check(lib().sbp_gradient(h, int(nsteps), float(dt), res_ptr, int(every), ws_ptr, int(ws_bytes), grad_ptr,
                               qbar_ptr))
@@ -324,6 +334,25 @@ class Solver:
         out = self.torch.empty((9,) + self.shape, dtype=self.tdtype, device=self.device)
         sbp_adjoint_rhs(self.h, lam.data_ptr(), out.data_ptr(), ws, nbytes)
         return out
+
+    def step_checkpointed(self, nsteps, dt, every=100):
+        """step() that keeps checkpoints for gradient_from_checkpoints()."""
+        nbytes = sbp_adjoint_bytes(self.h, nsteps, every)
+        ws = self._adjoint_ws(nbytes)
+        sbp_step_checkpointed(self.h, nsteps, dt, every, ws, nbytes)
+        self._ck = (nsteps, every, ws, nbytes)
+
+    def gradient_from_checkpoints(self, residual, want_qbar=False):
+        """The gradient of the last step_checkpointed() run (see gradient())."""
+        nsteps, every, ws, nbytes = self._ck
+        res = residual.to(device=self.device, dtype=self.tdtype).contiguous()
+        if self.traces is None or res.numel() != nsteps * self.traces.shape[1] * 3:
+            raise ValueError("residual must have shape (nsteps, nrec, 3) for the receivers of record()")
+        grad = self.torch.empty((3,) + self.shape, dtype=self.tdtype, device=self.device)
+        qbar = self.torch.empty((9,) + self.shape, dtype=self.tdtype, device=self.device) if want_qbar else None
+        sbp_gradient_from_checkpoints(self.h, res.data_ptr(), ws, nbytes, grad.data_ptr(),
+                                      qbar.data_ptr() if want_qbar else None)
+        return (grad, qbar) if want_qbar else grad
 
     def gradient(self, nsteps, dt, residual, every=100, want_qbar=False):
         """d chi / d (rho, lambda, mu) as a (3, ns, nr, nq) tensor (and d chi /

@@ -151,6 +151,37 @@ def test_gradient_matches_oracle(order, shape, nsteps, every, variant, dtype):
     s.close()
 
 
+def test_gradient_from_checkpoints_equals_gradient():
+    """A checkpointed forward run (sbp_step_checkpointed) followed by the
+    reverse sweep alone (sbp_gradient_from_checkpoints) gives bitwise the
+    gradient of sbp_gradient from the same initial state, twice in a row;
+    the traces equal those of sbp_step; stepping again invalidates the
+    checkpoints."""
+    say("case: gradient from checkpoints 17^3 order 6 f64 14 steps every 6")
+    sbp = sbp_mod()
+    c = gradient_case(6, (17, 17, 17), 14)
+    s = lib_solver(c, "f64")
+    tr_plain = lib_traces(s, c)
+    s.set_state(c["Q0"], 0.0)
+    tr = s.record(c["rec"], c["nsteps"])
+    s.step_checkpointed(c["nsteps"], c["dt"], 6)
+    tr_ck = tr.cpu().numpy().astype(np.float64)
+    assert np.array_equal(tr_ck, tr_plain)
+    res = torch.from_numpy(tr_ck - c["target"])
+    g1, q1 = s.gradient_from_checkpoints(res, want_qbar=True)
+    g1, q1 = g1.cpu().numpy(), q1.cpu().numpy()
+    g2 = s.gradient_from_checkpoints(res).cpu().numpy()
+    s.set_state(c["Q0"], 0.0)
+    s.record(c["rec"], c["nsteps"])
+    g3, q3 = s.gradient(c["nsteps"], c["dt"], res, 6, want_qbar=True)
+    assert np.array_equal(g1, g2)
+    assert np.array_equal(g1, g3.cpu().numpy()) and np.array_equal(q1, q3.cpu().numpy())
+    with pytest.raises(sbp.SBPError) as e:   # the handle moved on
+        s.gradient_from_checkpoints(res)
+    assert e.value.code == sbp.SBP_ESTATE
+    s.close()
+
+
 def test_gradient_matches_finite_differences_fp64():
     """d chi / d m along random directions in rho, lambda and mu against
     central differences of chi computed from the library's own FP64 forward
