@@ -451,7 +451,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver is a single-block, single-GPU build "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented).", file=sys.stderr)
+              "(sharding across GPUs is not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
