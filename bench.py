@@ -450,7 +450,7 @@ def main():
                     help="only run a plain device copy of MIB MiB (x4) for HBM counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the solver is a single-block, single-GPU build "
+        print("bench.py runs on one GPU only: the solver advances one block on one GPU "
               "(sharding across GPUs is not implemented).", file=sys.stderr)
         sys.exit(2)
 
