@@ -26,16 +26,19 @@ constructs its own closures:
 
 The accuracy conditions on the first m = order rows are linear in (w, free
 block of A); they are solved exactly.  For orders 2 and 4 the solution is
-unique.  For orders 3, 5, 6 and 7 entries of the free block stay free (one,
-two, one, four) and are fixed (FREE_ENTRIES) at values where the one-dimensional
+unique.  For orders 3, 5, 6, 7 and 8 entries of the free block stay free
+(one, two, one, four, three) and are fixed (FREE_ENTRIES) at values where the one-dimensional
 elastic operator with characteristic boundary penalties has the smallest
 spectral radius — no larger than the interior stencil's max |alpha^| — with
 positive norm weights, taking the simplest rational among equivalent values:
 order 3 A[1][2] = 1/2 (w = 7/12, 3/4, 7/6), order 5 A[2][4] = 1/4,
 A[3][4] = 1/2 (w = 323/720, 203/240, 71/48, 451/720, 11/10), order 6
 A[4][5] = 101/125, order 7 A[5][6] = 2/3, A[4][6] = A[3][6] = 0,
-A[4][5] = 3/5 (radius 1.7495 at N = 120 against the interior 1.7504) (a
-reading; the paper is silent).
+A[4][5] = 3/5 (radius 1.7495 at N = 120 against the interior 1.7504), order
+8 A[6][7] = 5/6, A[5][7] = -1/5, A[5][6] = 3/4 (radius 2.352 at N = 80
+against the interior 2.099: the radius depends sharply on these entries and
+its minimum over them, about 2.24, lies at irrational values) (a reading; the
+paper is silent).  Order 9 leaves seven entries free and is not constructed.
 S annihilates polynomials of degree < P, so D+ and D- share the accuracy of
 A + B/2.  The SBP identity and the semi-definiteness then hold by
 construction and are pinned separately by the tests.
@@ -64,7 +67,7 @@ UPWIND_ALPHA = {
 }
 
 # Orders whose boundary closures this oracle constructs.
-CLOSED_ORDERS = (2, 3, 4, 5, 6, 7)
+CLOSED_ORDERS = (2, 3, 4, 5, 6, 7, 8)
 
 # Free closure entries (see module docstring).
 ORDER6_FREE_A45 = Fr(101, 125)
@@ -73,6 +76,7 @@ FREE_ENTRIES = {
     5: {(2, 4): Fr(1, 4), (3, 4): Fr(1, 2)},
     6: {(4, 5): ORDER6_FREE_A45},
     7: {(5, 6): Fr(2, 3), (4, 6): Fr(0), (3, 6): Fr(0), (4, 5): Fr(3, 5)},
+    8: {(6, 7): Fr(5, 6), (5, 7): Fr(-1, 5), (5, 6): Fr(3, 4)},
 }
 
 

@@ -23,7 +23,7 @@ from oracle.elastic import AXIS, FACES
 
 def make_block(order, shape=None, seed=0, warped=True):
     # at least 2 m points per axis (m = order closure rows)
-    shape = shape or ((13, 12, 14) if order <= 6 else (15, 14, 16))
+    shape = shape or ((13, 12, 14) if order <= 6 else ((15, 14, 16) if order == 7 else (17, 16, 18)))
     ns, nr, nq = shape
     xyz = W.warped_mesh(nq, nr, ns, seed) if warped else W.unit_cube(nq, nr, ns)
     blk = E.Block(xyz, order)
@@ -121,7 +121,7 @@ def sat_dissipation(blk, Q, gamma):
     return tot
 
 
-@pytest.mark.parametrize("order", [2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("order", [2, 3, 4, 5, 6, 7, 8])
 def test_volume_terms_give_surface_term(order):
     blk = make_block(order, seed=order)
     Q = W.random_state(blk.shape, 10 + order)
@@ -147,7 +147,7 @@ def test_negative_control_same_operator_breaks_identity():
     assert abs(got - want) > 1e-3 * abs(want)
 
 
-@pytest.mark.parametrize("order", [2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("order", [2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("gseed", [0, 1])
 def test_characteristic_sat_energy_rate(order, gseed):
     blk = make_block(order, seed=20 + order)

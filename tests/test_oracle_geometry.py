@@ -20,10 +20,10 @@ def affine_mesh(shape, seed):
     return X, A
 
 
-@pytest.mark.parametrize("order", [2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("order", [2, 3, 4, 5, 6, 7, 8])
 def test_affine_map_metrics_exact(order):
     """For x = A xi + b: J = det A and M = J dxi/dx = J A^{-1} (Sec. 2.2)."""
-    X, A = affine_mesh((15, 14, 16) if order > 6 else (13, 14, 12), order)
+    X, A = affine_mesh((17, 16, 18) if order > 6 else (13, 14, 12), order)
     blk = E.Block(X, order)
     J = np.linalg.det(A)
     Ainv = np.linalg.inv(A)
@@ -33,10 +33,10 @@ def test_affine_map_metrics_exact(order):
             assert np.allclose(blk.M[xi][c], J * Ainv[xi, c], rtol=0, atol=1e-11 * abs(J))
 
 
-@pytest.mark.parametrize("order", [2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("order", [2, 3, 4, 5, 6, 7, 8])
 def test_discrete_metric_identity(order):
     """sum_xi D-_xi M[xi][c] = 0 for the conservative cofactor metrics."""
-    X = W.warped_mesh(14, 15, 15, seed=order)
+    X = W.warped_mesh(16, 17, 16, seed=order)
     blk = E.Block(X, order)
     for c in range(3):
         s = sum(E.apply_along(blk.ops[xi]["Dm"], blk.M[xi][c], xi) for xi in range(3))
@@ -86,7 +86,7 @@ def test_metrics_converge_to_analytic(order):
     assert rates[-1] > order // 2 - 0.3, rates
 
 
-@pytest.mark.parametrize("order", [2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("order", [2, 3, 4, 5, 6, 7, 8])
 def test_discrete_delta_moments(order):
     """sum_ijk H_ijk J_ijk delta_ijk f_ijk = f(x_s) for tensor polynomials of
     degree < 2(p+1) per reference axis, including near a boundary."""

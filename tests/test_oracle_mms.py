@@ -91,6 +91,7 @@ def mms_error(order, n, warped, gamma, T=0.05, cfl=0.25):
     (5, (13, 19, 25, 37), False),
     (5, (13, 19, 25, 37), True),
     (7, (15, 21, 29, 41), False),
+    (8, (17, 23, 31, 41), False),
     (6, (13, 19, 25, 37), False),
     (6, (13, 19, 25, 37), True),
 ])
