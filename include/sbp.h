@@ -84,6 +84,12 @@ int sbp_workspace_bytes(int nq, int nr, int ns, int order, int dtype, size_t* by
  *  nq, nr, ns   points along q, r, s (uniform reference grid xi_i = i / (n-1),
  *               Sec. 4.1); each must be >= 2 * order so that the two
  *               boundary closures of the SBP operators do not overlap.
+ *               One field of the device layout must stay below 4 GiB (the
+ *               kernels address a field with 32-bit byte offsets): rows of
+ *               nq - 1 points padded to 128 bytes, nr * ns of them, plus
+ *               the last column, i.e. about 1.07e9 points for SBP_F32
+ *               (1025 x 1024 x 1023 passes, 1025 x 1024 x 1024 does not)
+ *               and 5.4e8 for SBP_F64.  Larger grids are SBP_EINVAL.
  *  xyz          host, 3 * nq * nr * ns doubles: x, then y, then z, each a
  *               grid function.  NULL selects the identity map of the unit
  *               cube.  Metric terms are computed on the host in double
@@ -276,6 +282,17 @@ int sbp_energy(sbp_handle h, double* E);
  * not change it at all: every node is computed by the same instructions).
  */
 int sbp_set_launch(sbp_handle h, int ty, int zchunk);
+
+/*
+ * Addressing of the stage kernel's field arrays.  plain = 0 (default):
+ * buffer resources (32-bit offsets from one descriptor per array) whenever
+ * every array of up to 12 fields is below 4 GiB, plain 64-bit pointers
+ * otherwise; plain = 1: plain pointers always, the path large grids take,
+ * on any grid.  Results agree to rounding (two instantiations of the same
+ * kernel body; the compiler may contract differently).  SBP_EINVAL for
+ * other values.
+ */
+int sbp_set_addressing(sbp_handle h, int plain);
 
 /*
  * Launch timing.  sbp_set_profiling(h, 1) resets the counters and from then

@@ -105,6 +105,7 @@ struct sbp_ctx {
   long long rec_step = 0;
   void* rec_out = nullptr;
   int ty = 8, zchunk = 0;
+  bool plain = false;   // plain pointers even where buffer addressing fits (sbp_set_addressing)
   int nxt = 0, nyt = 0, nzc = 0;
   int ex = 0, ey = 0;   // last q column / last r row computed by the edge kernel
   bool bounds_dirty = true;
@@ -124,6 +125,19 @@ struct sbp_ctx {
 
 namespace {
 
+// The first nq - 1 columns in rows starting on 128-byte lines (the memory
+// request size); column nq - 1 in a compact array after them (NodeMap).
+std::size_t row_pitch(int nq, std::size_t es) {
+  const std::size_t line = 128 / es;
+  return ((std::size_t)nq - 1 + line - 1) / line * line;
+}
+
+// elements of one field
+std::size_t field_elems(int nq, int nr, int ns, std::size_t es) {
+  const std::size_t line = 128 / es, ncol = (std::size_t)nr * ns;
+  return row_pitch(nq, es) * ncol + (ncol + line - 1) / line * line;
+}
+
 int check_dims(int nq, int nr, int ns, int order, int dtype) {
   if (order == 8 || order == 9)
     return fail(SBP_EINVAL, "order %d is not supported: its 5-point halo does not fit the 8-row stage tiles", order);
@@ -136,8 +150,13 @@ int check_dims(int nq, int nr, int ns, int order, int dtype) {
     return fail(SBP_EINVAL, "every axis needs at least %d points for order %d (got %d x %d x %d)", mn, order, nq,
                 nr, ns);
   if (nq > 1 << 20 || nr > 1 << 20 || ns > 1 << 20) return fail(SBP_EINVAL, "axis too long");
-  const double n = (double)nq * nr * ns;
-  if (n > 4.0e9) return fail(SBP_EINVAL, "grid too large");
+  // the kernels address a field with 32-bit byte offsets: one field of the
+  // layout must stay below 4 GiB
+  const std::size_t es = dtype == SBP_F32 ? 4 : 8;
+  const std::size_t bytes = field_elems(nq, nr, ns, es) * es;
+  if (bytes >= ((std::size_t)1 << 32))
+    return fail(SBP_EINVAL, "grid too large: one field takes %zu bytes, the kernels address at most 4 GiB per field",
+                bytes);
   return SBP_OK;
 }
 
@@ -168,13 +187,9 @@ std::size_t batch_region_bytes() { return batch_region().total; }
 void layout(sbp_ctx* h) {
   const int es = h->esize;
   const Geometry& g = h->g;
-  // The first nq - 1 columns in rows starting on 128-byte lines (the memory
-  // request size); column nq - 1 in a compact array after them (NodeMap).
-  const int line = 128 / es;
-  h->px = (g.nq - 1 + line - 1) / line * line;
+  h->px = (int)row_pitch(g.nq, es);
   h->plane = (std::size_t)h->px * g.nr;
-  const std::size_t ncol = (std::size_t)g.nr * g.ns;
-  h->field = h->plane * g.ns + (ncol + line - 1) / line * line;
+  h->field = field_elems(g.nq, g.nr, g.ns, es);
   h->nm.plane = (long long)h->plane;
   h->nm.cbase = (long long)(h->plane * g.ns);
   h->nm.px = h->px;
@@ -509,6 +524,7 @@ StageArgs<T> stage_args(sbp_ctx* h) {
   a.ex = h->ex;
   a.ey = h->ey;
   a.sat = 1;
+  a.plain = h->plain ? 1 : 0;
   a.plane = h->plane;
   a.field = h->field;
   a.px = h->px;
@@ -714,7 +730,7 @@ int do_steps_batch(sbp_ctx** hs, int n, int nsteps, const double* dt) {
       fe[q] = te;
       ts += a.ntiles;
       te += edge_blocks(a);
-      buf_ok = buf_ok && 12.0 * (double)a.field * sizeof(T) < 4294967296.0;
+      buf_ok = buf_ok && !a.plain && 12.0 * (double)a.field * sizeof(T) < 4294967296.0;
     }
     fs[gstart[G + 1] - gstart[G]] = ts;
     fe[gstart[G + 1] - gstart[G]] = te;
@@ -1584,6 +1600,13 @@ int sbp_set_launch(sbp_handle h, int ty, int zchunk) {
   h->ty = ty;
   h->zchunk = zchunk;
   h->bounds_dirty = true;
+  return SBP_OK;
+}
+
+int sbp_set_addressing(sbp_handle h, int plain) {
+  if (!h) return fail(SBP_EINVAL, "NULL handle");
+  if (plain != 0 && plain != 1) return fail(SBP_EINVAL, "plain must be 0 or 1");
+  h->plain = plain == 1;
   return SBP_OK;
 }
 

@@ -1155,7 +1155,7 @@ static hipError_t launch_stage_t(const StageArgs<T>& a, hipStream_t st) {
   } else {
     const int nb = ((a.ntiles + 7) / 8) * 8;
     // buffer addressing needs every array (at most 12 fields) below 4 GiB
-    if (12.0 * (double)a.field * sizeof(T) < 4294967296.0)
+    if (!a.plain && 12.0 * (double)a.field * sizeof(T) < 4294967296.0)
       hipLaunchKernelGGL((stage_kernel<T, ORDER, TY, true>), dim3(nb), dim3(64, TY), 0, st, a);
     else
       hipLaunchKernelGGL((stage_kernel<T, ORDER, TY, false>), dim3(nb), dim3(64, TY), 0, st, a);

@@ -27,6 +27,7 @@ struct StageArgs {
   int read_dq;
   int ex, ey;         // edge kernel: last q column / last r row
   int sat;            // 1: boundary penalties on; 0: volume terms only
+  int plain;          // 1: plain pointers even where buffer addressing fits
   int traction[6];
   T Ak, Bk, dt;
   T inv_h[3];

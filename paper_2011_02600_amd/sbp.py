@@ -54,6 +54,7 @@ def lib():
             "sbp_set_launch": [c_void_p, c_int, c_int],
             "sbp_time": [c_void_p, P(c_double), P(ctypes.c_longlong)],
             "sbp_set_profiling": [c_void_p, c_int],
+            "sbp_set_addressing": [c_void_p, c_int],
             "sbp_step_batch": [c_void_p, c_int, c_int, P(c_double)],
             "sbp_autotune": [c_void_p, c_int, P(c_int), P(c_int), P(c_double)],
             "sbp_profile": [c_void_p, P(c_double), P(c_double), P(ctypes.c_longlong), P(ctypes.c_longlong)],
@@ -172,6 +173,10 @@ def sbp_autotune(h, reps=5):
     ty, zc, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
     _check(lib().sbp_autotune(h, int(reps), ctypes.byref(ty), ctypes.byref(zc), ctypes.byref(ms)))
     return ty.value, zc.value, ms.value
+
+
+def sbp_set_addressing(h, plain):
+    _check(lib().sbp_set_addressing(h, int(plain)))
 
 
 def sbp_set_profiling(h, on):
@@ -303,6 +308,9 @@ class Solver:
 
     def set_launch(self, ty=8, zchunk=0):
         sbp_set_launch(self.h, ty, zchunk)
+
+    def set_addressing(self, plain):
+        sbp_set_addressing(self.h, plain)
 
     def autotune(self, reps=5):
         return sbp_autotune(self.h, reps)

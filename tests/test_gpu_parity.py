@@ -259,6 +259,47 @@ def test_launch_shapes_give_identical_results(size):
     assert err < 1e-5
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_plain_pointer_addressing(dtype):
+    """The plain-pointer stage kernel (the path grids with arrays of 4 GiB and
+    more take) on a small grid, forced by sbp_set_addressing: 10 steps with
+    sources agree with the buffer-addressed kernel to rounding, single and
+    batched, and the state after them with the oracle."""
+    nq, nr, ns = 65, 41, 33
+    say("case: plain-pointer addressing order 6 %s %dx%dx%d" % (dtype, nq, nr, ns))
+    sbp = sbp_mod()
+    xyz = W.warped_mesh(nq, nr, ns, seed=5)
+    med = W.random_medium((ns, nr, nq), 8)
+    Q = W.random_state((ns, nr, nq), 9, smooth=True)
+    gamma = [1, 0, 0.5, 0, -1, 1]
+    src = ((0.4, 0.55, 0.5), (0.2, 0.1, -0.3, 1.0, 0.0, 0.4), 0, 8.0, 0.05)
+    out = {}
+    for mode in ("buffer", "plain", "plain batch"):
+        s = make_solver(xyz, 6, dtype, gamma, medium=med)
+        s.add_source(*src)
+        s.set_state(Q)
+        if mode != "buffer":
+            s.set_addressing(1)
+        if mode == "plain batch":
+            sbp.sbp_step_batch([s.h], 10, [1e-3])
+        else:
+            s.step(10, 1e-3)
+        out[mode] = s.get_state().cpu().numpy().astype(np.float64)
+        s.close()
+    tol = 1e-5 if dtype == "f32" else 1e-12
+    e1 = rel_max(out["plain"], out["buffer"])
+    e2 = rel_max(out["plain batch"], out["buffer"])
+    blk = E.Block(xyz, 6).set_material(*med)
+    osrc = E.Source(blk, src[0], src[1], E.STF_RICKER, src[3], src[4])
+    want, _, _ = E.run(blk, Q, 10, 1e-3, gamma, sources=[osrc])
+    e3 = rel_l2(out["plain"], want)
+    say("  plain vs buffer %.2e, plain batched vs buffer %.2e, plain vs oracle %.2e" % (e1, e2, e3))
+    assert e1 <= tol and e2 <= tol
+    assert e3 <= TOL[dtype]
+    with pytest.raises(sbp.SBPError):
+        sbp.sbp_set_addressing(None, 1)
+
+
 def test_resume_is_bitwise():
     say("case: resume 20 + 20 == 40 steps, order 6 f32")
     wl = W.topo_layer(nq=33, nr=29, ns=25)
@@ -309,6 +350,33 @@ def test_error_paths_on_device():
     with pytest.raises(sbp.SBPError) as e:
         sbp.Solver(bad, order=4, dtype="f32", gamma=[0] * 6)
     assert e.value.code == sbp.SBP_EINVAL
+
+
+def test_degenerate_calls():
+    """Zero steps (single or batched) change nothing: the state bitwise, the
+    time and the step count; an empty handle list is SBP_EINVAL; an empty
+    receiver list switches recording off and stepping goes on."""
+    say("case: degenerate calls, order 4 f32 17x15x13")
+    sbp = sbp_mod()
+    nq, nr, ns = 17, 15, 13
+    s = make_solver(W.warped_mesh(nq, nr, ns, seed=4), 4, "f32", [1, 0, 0, 0, 0, 1],
+                    medium=W.random_medium((ns, nr, nq), 2))
+    s.set_state(W.random_state((ns, nr, nq), 3, smooth=True))
+    before = s.get_state().cpu().numpy()
+    s.step(0, 1e-3)
+    sbp.sbp_step_batch([s.h], 0, [1e-3])
+    assert np.array_equal(s.get_state().cpu().numpy(), before)
+    assert s.time() == (0.0, 0)
+    with pytest.raises(sbp.SBPError) as e:
+        sbp.sbp_step_batch([], 1, [])
+    assert e.value.code == sbp.SBP_EINVAL
+    s.record([(1, 2, 3)], 1)
+    s.step(1, 1e-3)
+    s.record(np.zeros((0, 3), dtype=np.int32), 1)
+    s.step(3, 1e-3)
+    assert s.time()[1] == 4
+    assert np.all(np.isfinite(s.get_state().cpu().numpy()))
+    s.close()
 
 
 def test_profiling_changes_nothing():

@@ -50,6 +50,24 @@ def test_workspace_size_and_validation():
         sbp.sbp_workspace_bytes(2 * order, 2 * order, 2 * order, order, sbp.SBP_F32)
 
 
+def test_field_size_limit():
+    """The kernels address one field with 32-bit byte offsets: grids whose
+    field (rows padded to 128 bytes plus the last column) reaches 4 GiB are
+    rejected, the largest ones below are accepted."""
+    b = sbp.sbp_workspace_bytes(1025, 1024, 1023, 6, sbp.SBP_F32)
+    assert b >= 39 * 1024 * 1024 * 1023 * 4
+    sbp.sbp_workspace_bytes(1025, 1024, 511, 6, sbp.SBP_F64)
+    for args in [(1025, 1024, 1024, 6, sbp.SBP_F32), (1025, 1024, 512, 6, sbp.SBP_F64),
+                 (4000, 4000, 4000, 4, sbp.SBP_F32), (1 << 20, 1 << 20, 1 << 20, 4, sbp.SBP_F32)]:
+        with pytest.raises(sbp.SBPError) as e:
+            sbp.sbp_workspace_bytes(*args)
+        assert e.value.code == sbp.SBP_EINVAL
+        assert "4 GiB" in str(e.value)
+    with pytest.raises(sbp.SBPError) as e:
+        sbp.sbp_init_grid(1025, 1024, 1024, None, 6, sbp.SBP_F32, np.zeros(6), 0, 256, 1 << 40, None)
+    assert e.value.code == sbp.SBP_EINVAL
+
+
 def test_init_rejects_bad_arguments_before_device_use():
     g_ok = np.zeros(6)
     fake = 256  # never dereferenced: validation fails first
