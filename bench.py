@@ -88,9 +88,10 @@ def read_traffic():
         return None
 
 
-def cpu_baseline(wl, order=6, nstages=2):
+def cpu_baseline(wl, order=6, nstages=5):
     """The CPU oracle as it stands, timed on the host: `nstages` Runge-Kutta
-    stages (right-hand side + stage update) of the full workload."""
+    stages (right-hand side + stage update; at most 5, one whole step) of the
+    full workload."""
     import numpy as np
     from oracle import elastic as E
     from oracle import lsrk
