@@ -433,6 +433,8 @@ def main():
                     help="steps of the stage-kernel-only timing region")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--ty", type=int, default=8)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"],
+                    help="arithmetic of the topo_layer workload (f64: order 2 to 6)")
     ap.add_argument("--zchunk", type=int, default=0)
     ap.add_argument("--order", type=int, default=6, choices=[2, 3, 4, 5, 6, 7],
                     help="interior order of the topo_layer run (the headline workload is order 6)")
@@ -492,7 +494,7 @@ def main():
     ns, nr, nq = wl["xyz"].shape[1:]
     nodes = nq * nr * ns
     order = args.order
-    s = sbp.Solver(wl["xyz"], order=order, dtype="f32", gamma=wl["gamma"], device=dev)
+    s = sbp.Solver(wl["xyz"], order=order, dtype=args.dtype, gamma=wl["gamma"], device=dev)
     s.set_material(wl["rho"], wl["cp"], wl["cs"])
     s.set_launch(args.ty, args.zchunk)
     s.add_source(wl["src_xi"], wl["src_M"], sbp.SBP_STF_RICKER, wl["src_f0"], wl["src_t0"])
@@ -540,13 +542,16 @@ def main():
     s.step(args.kernel_steps // 4, dt)
     launch_ms, edge_ms, nprof, stage_nodes = s.profile()
     s.set_profiling(False)
-    bytes_per_launch = WORDS_AVG * 4 * stage_nodes
+    wbytes = 4 if args.dtype == "f32" else 8
+    bytes_per_launch = WORDS_AVG * wbytes * stage_nodes
     achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9
-    traffic = read_traffic() if order == 6 else None  # the counters were taken at order 6
+    # the counters were taken at order 6 in single precision
+    traffic = read_traffic() if order == 6 and args.dtype == "f32" else None
     s.close()
 
     out = {
-        "metric": "Mpts*stage/s (order-%d FP32 curvilinear RHS + LSRK4 stage update)" % order,
+        "metric": "Mpts*stage/s (order-%d %s curvilinear RHS + LSRK4 stage update)"
+                  % (order, {"f32": "FP32", "f64": "FP64"}[args.dtype]),
         "value": round(value, 2),
         "unit": "Mpts*stage/s",
         "n_gpus": 1,
@@ -556,7 +561,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.dtype,
         "data": "synthetic",
         "config": {"workload": "topo_layer: order-%d upwind SBP, curvilinear 257x257x193 (q,r,s) block under "
                                % order +
@@ -568,7 +573,8 @@ def main():
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": None if traffic is None else int(traffic),
                      "traffic_rate_gbs": None if traffic is None else round(traffic / (launch_ms / 1e3) / 1e9, 1),
-                     "kernel": "stage_kernel<float,%d,%d>" % (order, args.ty),
+                     "kernel": "stage_kernel<%s,%d,%d>" % ("float" if args.dtype == "f32" else "double", order,
+                                                            args.ty),
                      "avg_launch_ms": round(launch_ms, 4),
                      "launches_timed": nprof,
                      "nodes_per_launch": stage_nodes,
