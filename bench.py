@@ -45,11 +45,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-# algorithmic words per node per stage: read Q_in (9) + coefficients (12),
-# read the Runge-Kutta register (9, stages 2-5 only), write it (9) and Q_out (9)
-WORDS_STAGE1 = 9 + 12 + 9 + 9
+# algorithmic words per node per stage: read Q_in (9) + 13 coefficients (the
+# nine metric terms, J^-1, (rho J)^-1, lambda, mu), read the Runge-Kutta
+# register (9, stages 2-5 only), write it (9) and Q_out (9): 40 words in the
+# first stage, 49 in the others, 47.2 on average
+WORDS_STAGE1 = 9 + 13 + 9 + 9
 WORDS_STAGE = WORDS_STAGE1 + 9
 WORDS_AVG = (WORDS_STAGE1 + 4 * WORDS_STAGE) / 5.0
+# the library stores 12 coefficient words (J folded into lambda/J, mu/J and
+# 1/(rho J)): 46.2 words on average, reported beside the figure above
+WORDS_AVG_STORED = WORDS_AVG - 1.0
 PROFILE = os.path.join(ROOT, "profiles", "stage_kernel_topo_layer_257x257x193.md")
 CSRC = os.path.join(ROOT, "paper_2011_02600_amd", "csrc")
 
@@ -432,6 +437,8 @@ def main():
     ap.add_argument("--kernel-steps", type=int, default=200,
                     help="steps of the stage-kernel-only timing region")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the double-precision run of the same workload (the fp64 object)")
     ap.add_argument("--ty", type=int, default=8)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"],
                     help="arithmetic of the topo_layer workload (f64: order 2 to 6)")
@@ -494,14 +501,58 @@ def main():
     ns, nr, nq = wl["xyz"].shape[1:]
     nodes = nq * nr * ns
     order = args.order
-    s = sbp.Solver(wl["xyz"], order=order, dtype=args.dtype, gamma=wl["gamma"], device=dev)
+    m = measure_topo(args, wl, args.dtype, order, sbp, torch, np, dev)
+    traffic = read_traffic() if order == 6 and args.dtype == "f32" else None
+    out = {
+        "metric": "Mpts*stage/s (order-%d %s curvilinear RHS + LSRK4 stage update)"
+                  % (order, {"f32": "FP32", "f64": "FP64"}[args.dtype]),
+        "value": m["value"],
+        "unit": "Mpts*stage/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": "topo_layer: order-%d upwind SBP, curvilinear 257x257x193 (q,r,s) block under "
+                               % order +
+                               "seeded topography, 1 km layer over half-space, Ricker moment source, "
+                               "64 surface receivers, CFL %.2g" % (0.5 if order == 6 else 0.25),
+                   "grid": [nq, nr, ns], "nodes": nodes, "order": order, "dt": wl["dt"],
+                   "launch": {"ty": args.ty, "zchunk": args.zchunk}},
+        "roofline": dict(m["roofline"], traffic=None if traffic is None else int(traffic),
+                         traffic_rate_gbs=None if traffic is None
+                         else round(traffic / (m["roofline"]["avg_launch_ms"] / 1e3) / 1e9, 1)),
+    }
+    if not args.no_fp64 and args.dtype == "f32":
+        # the same workload in the paper's arithmetic (double precision)
+        m64 = measure_topo(args, wl, "f64", order, sbp, torch, np, dev)
+        out["fp64"] = {"value": m64["value"], "unit": "Mpts*stage/s", "ms_per_step": m64["ms_per_step"],
+                       "steps": args.steps, "roofline": m64["roofline"]}
+    if not args.no_cpu:
+        print("bench: cpu oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, order)
+    print(json.dumps(out), flush=True)
+
+
+def measure_topo(args, wl, dtype, order, sbp, torch, np, dev):
+    """Times the topo_layer workload in `dtype`: `args.steps` whole steps
+    (stages, source, receivers) after `args.warmup` untimed ones, then the
+    Runge-Kutta stage alone and the stage kernel's launches (library events
+    on the solver's stream)."""
+    ns, nr, nq = wl["xyz"].shape[1:]
+    nodes = nq * nr * ns
+    s = sbp.Solver(wl["xyz"], order=order, dtype=dtype, gamma=wl["gamma"], device=dev)
     s.set_material(wl["rho"], wl["cp"], wl["cs"])
     s.set_launch(args.ty, args.zchunk)
     s.add_source(wl["src_xi"], wl["src_M"], sbp.SBP_STF_RICKER, wl["src_f0"], wl["src_t0"])
     s.record(wl["receivers"], args.warmup + args.steps)
     stream = s.stream
     dt = wl["dt"]
-    print("bench: warmup", file=sys.stderr, flush=True)
+    print("bench: %s warmup" % dtype, file=sys.stderr, flush=True)
     s.step(args.warmup, dt)
     torch.cuda.synchronize()
 
@@ -521,8 +572,8 @@ def main():
     traces = s.traces.float().cpu().numpy()
     if not np.all(np.isfinite(traces)):
         raise RuntimeError("non-finite receiver traces")
-    print("bench: %d steps in %.3f s (events) / %.3f s (wall)" % (args.steps, secs, wall), file=sys.stderr,
-          flush=True)
+    print("bench: %s %d steps in %.3f s (events) / %.3f s (wall)" % (dtype, args.steps, secs, wall),
+          file=sys.stderr, flush=True)
 
     # ---- the Runge-Kutta stage alone (same solver, no source, no receivers):
     # events on the solver's stream around the steps (stage + edge kernel per
@@ -542,51 +593,25 @@ def main():
     s.step(args.kernel_steps // 4, dt)
     launch_ms, edge_ms, nprof, stage_nodes = s.profile()
     s.set_profiling(False)
-    wbytes = 4 if args.dtype == "f32" else 8
+    s.close()
+    wbytes = 4 if dtype == "f32" else 8
     bytes_per_launch = WORDS_AVG * wbytes * stage_nodes
     achieved = bytes_per_launch / (launch_ms / 1e3) / 1e9
-    # the counters were taken at order 6 in single precision
-    traffic = read_traffic() if order == 6 and args.dtype == "f32" else None
-    s.close()
-
-    out = {
-        "metric": "Mpts*stage/s (order-%d %s curvilinear RHS + LSRK4 stage update)"
-                  % (order, {"f32": "FP32", "f64": "FP64"}[args.dtype]),
-        "value": round(value, 2),
-        "unit": "Mpts*stage/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms / args.steps, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": args.dtype,
-        "data": "synthetic",
-        "config": {"workload": "topo_layer: order-%d upwind SBP, curvilinear 257x257x193 (q,r,s) block under "
-                               % order +
-                               "seeded topography, 1 km layer over half-space, Ricker moment source, "
-                               "64 surface receivers, CFL %.2g" % (0.5 if order == 6 else 0.25),
-                   "grid": [nq, nr, ns], "nodes": nodes, "order": order, "dt": dt,
-                   "launch": {"ty": args.ty, "zchunk": args.zchunk}},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4),
-                     "traffic": None if traffic is None else int(traffic),
-                     "traffic_rate_gbs": None if traffic is None else round(traffic / (launch_ms / 1e3) / 1e9, 1),
-                     "kernel": "stage_kernel<%s,%d,%d>" % ("float" if args.dtype == "f32" else "double", order,
-                                                            args.ty),
-                     "avg_launch_ms": round(launch_ms, 4),
-                     "launches_timed": nprof,
-                     "nodes_per_launch": stage_nodes,
-                     "algorithmic_bytes_per_launch": int(bytes_per_launch),
-                     "words_per_node": WORDS_AVG,
-                     "edge_kernel_avg_launch_ms": round(edge_ms, 4),
-                     "rk_stage_ms": round(rk_stage_ms, 4)},
-    }
-    if not args.no_cpu:
-        print("bench: cpu oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl, order)
-    print(json.dumps(out), flush=True)
+    achieved_stored = WORDS_AVG_STORED * wbytes * stage_nodes / (launch_ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(achieved / PEAK_HBM_GBS, 4),
+            "traffic": None,
+            "kernel": "stage_kernel<%s,%d,%d>" % ("float" if dtype == "f32" else "double", order, args.ty),
+            "avg_launch_ms": round(launch_ms, 4),
+            "launches_timed": nprof,
+            "nodes_per_launch": stage_nodes,
+            "algorithmic_bytes_per_launch": int(bytes_per_launch),
+            "words_per_node": WORDS_AVG,
+            "frac_stored_words": round(achieved_stored / PEAK_HBM_GBS, 4),
+            "stored_words_per_node": WORDS_AVG_STORED,
+            "edge_kernel_avg_launch_ms": round(edge_ms, 4),
+            "rk_stage_ms": round(rk_stage_ms, 4)}
+    return {"value": round(value, 2), "ms_per_step": round(ms / args.steps, 4), "roofline": roof}
 
 
 if __name__ == "__main__":

@@ -141,6 +141,26 @@ int sbp_set_material(sbp_handle h, const double* rho, const double* cp, const do
 int sbp_add_source(sbp_handle h, const double* xi, const double* M, int stf, double param,
                    double t0);
 
+/*
+ * Reference coordinates of a physical point (the source position x_p of
+ * eq. momententor_pointsource is a physical point): xi (host, 3 doubles,
+ * (q, r, s) in [0, 1]^3) with X(xi) = x (host, 3 doubles), X the
+ * tensor-product Lagrange interpolant of the node coordinates over the
+ * 2(p+1) nearest nodes per axis (the window of the discrete delta).
+ * Newton iteration started at the nearest node; the node coordinates are
+ * those given to sbp_init_grid.  SBP_EINVAL if the point lies outside the
+ * block (beyond a face by more than 1e-9 of the block's diagonal, in
+ * reference or physical distance) or the iteration does not converge.
+ */
+int sbp_locate(sbp_handle h, const double* x, double* xi);
+
+/*
+ * sbp_add_source with the source given at a physical position x (host, 3
+ * doubles): its reference coordinates come from sbp_locate.  Same arguments
+ * otherwise; SBP_EINVAL outside the block.
+ */
+int sbp_add_source_at(sbp_handle h, const double* x, const double* M, int stf, double param, double t0);
+
 /* Remove all sources. */
 int sbp_clear_sources(sbp_handle h);
 
@@ -172,8 +192,22 @@ int sbp_record(sbp_handle h, int nrec, const int* ijk, void* out_device, int max
  * (volume terms, penalties, sources) and is fused with the stage update
  * dQ <- A_k dQ + dt RHS, Q <- Q + B_k dQ.  Asynchronous on the stream.
  * SBP_ESTATE before sbp_set_material.
+ * Each step is one replay of a HIP graph holding the step's launches (five
+ * stages of stage, edge and source kernels, the receivers, a clock tick),
+ * captured on first use and again whenever dt, the sources, the receivers
+ * or the launch shape change.  The per-step values (the source-time factor
+ * dt g(t_n + C_k dt) of every stage, evaluated on the host in double, and
+ * the receiver slot) are read from a device table and a device step
+ * counter, uploaded / set once per 512 steps.
  */
 int sbp_step(sbp_handle h, int nsteps, double dt);
+
+/*
+ * on = 1 (default): sbp_step replays captured step graphs; on = 0: it
+ * issues the same launches one by one.  Results are bitwise identical.
+ * Profiling (sbp_set_profiling) uses the one-by-one launches.
+ */
+int sbp_set_graphs(sbp_handle h, int on);
 
 /*
  * Advance n handles (1 <= n <= 64) by nsteps steps each, handle i with step
@@ -256,6 +290,15 @@ int sbp_gradient(sbp_handle h, int nsteps, double dt, const void* residual_devic
 int sbp_step_checkpointed(sbp_handle h, int nsteps, double dt, int every, void* adj_ws, size_t adj_bytes);
 
 /*
+ * Identifier of the checkpoints sbp_gradient_from_checkpoints would use
+ * (> 0, a new value for every sbp_step_checkpointed call), or 0 if there
+ * are none (the handle was stepped, or its state, medium, sources or
+ * receivers changed since).  Lets a caller check that the checkpoints are
+ * still those of its own forward run.
+ */
+int sbp_checkpoint_id(sbp_handle h, long long* id);
+
+/*
  * The gradient of sbp_gradient for the run of the last sbp_step_checkpointed
  * on this handle (its nsteps, dt and every; adj_ws the same workspace), the
  * handle standing at the end of that run: only the reverse sweep.  Results
@@ -319,6 +362,16 @@ int sbp_profile(sbp_handle h, double* stage_ms, double* edge_ms, long long* nsta
  * it between steps.  Synchronises the stream.
  */
 int sbp_autotune(sbp_handle h, int reps, int* ty, int* zchunk, double* ms);
+
+/*
+ * Fill the handle's scratch buffers -- the state buffer that does not hold
+ * the current state (the next stage's output) and the Runge-Kutta register
+ * -- with `value` (for instance a NaN), asynchronously.  A check of the
+ * ping-pong design: every stage writes every node of its output before the
+ * next stage reads it, and the first stage does not read the register, so
+ * sbp_step and sbp_rhs results do not depend on these contents.
+ */
+int sbp_fill_scratch(sbp_handle h, double value);
 
 /* Current time and number of completed steps. */
 int sbp_time(sbp_handle h, double* t, long long* steps);

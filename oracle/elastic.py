@@ -262,6 +262,48 @@ def source_stencil(blk, xi3):
     return sl, w
 
 
+def _interp_map(blk, u):
+    """Node coordinates interpolated at u = (u_q, u_r, u_s) in node units:
+    tensor product of Lagrange polynomials over the 2(p+1) nodes nearest to u
+    per axis (the window of the discrete delta, ``delta_1d``)."""
+    width = 2 * (blk.order // 2 + 1)
+    bases = []
+    for a in range(3):
+        n = blk.npts[a]
+        start = min(max(int(np.floor(u[a])) - width // 2 + 1, 0), n - width)
+        nodes = start + np.arange(width)
+        L = np.ones(width)
+        for i in range(width):
+            for j in range(width):
+                if j != i:
+                    L[i] *= (u[a] - nodes[j]) / (nodes[i] - nodes[j])
+        bases.append((start, L))
+    (sq, Lq), (sr, Lr), (ss, Ls) = bases
+    sub = blk.xyz[:, ss:ss + width, sr:sr + width, sq:sq + width]
+    return np.einsum("ckji,k,j,i->c", sub, Ls, Lr, Lq)
+
+
+def locate(blk, x):
+    """Reference coordinates (q, r, s), each in [0, 1], of the physical point x
+    (reading: eq. momententor_pointsource places the source at a physical
+    point; between nodes the map is the Lagrange interpolant of the node
+    coordinates over the window of the discrete delta).  The root of
+    X(u) - x is found by scipy's fsolve from the nearest node; a root outside
+    the block raises ValueError."""
+    from scipy.optimize import fsolve
+    x = np.asarray(x, dtype=np.float64)
+    d2 = sum((blk.xyz[c] - x[c]) ** 2 for c in range(3))
+    k, j, i = np.unravel_index(np.argmin(d2), d2.shape)
+    u0 = np.array([i, j, k], dtype=np.float64)
+    u, info, ier, msg = fsolve(lambda u: _interp_map(blk, u) - x, u0, xtol=1e-14, full_output=True)
+    if ier != 1 and np.linalg.norm(_interp_map(blk, u) - x) > 1e-11 * np.ptp(blk.xyz):
+        raise ValueError("map not inverted: %s" % msg)
+    npm1 = np.array(blk.npts, dtype=np.float64) - 1
+    if np.any(u < -1e-9) or np.any(u > npm1 + 1e-9):
+        raise ValueError("point outside the block")
+    return tuple(np.clip(u, 0, npm1) / npm1)
+
+
 class Source:
     """sigma_dot += M g(t) delta_h (reading: added to the stress rates as
     printed, no stiffness factor)."""

@@ -5,8 +5,9 @@ The forward pass steps the solver keeping checkpoints
 (sbp_step_checkpointed, receivers recorded); the backward pass runs the
 library's discrete adjoint from those checkpoints
 (sbp_gradient_from_checkpoints) with the incoming gradient of the traces as
-the residual, or, if the solver was used in between, sbp_gradient from the
-saved initial state.  Argument marshalling only: all
+the residual when the solver's checkpoints are still those of this forward
+run (same checkpoint id), or else sbp_gradient from the saved initial
+state.  Argument marshalling only: all
 arithmetic of both passes runs in the HIP library.
 """
 import numpy as np
@@ -32,6 +33,7 @@ class Seismograms(torch.autograd.Function):
         solver.set_state(Q0, 0.0)
         traces = solver.record(receivers, nsteps)
         solver.step_checkpointed(nsteps, dt, every)
+        ctx.ck_id = solver.checkpoint_id()
         ctx.solver, ctx.Q0, ctx.receivers = solver, Q0, receivers
         ctx.nsteps, ctx.dt, ctx.every = nsteps, dt, every
         ctx.mat = (rho, lam, mu)
@@ -39,14 +41,12 @@ class Seismograms(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_traces):
-        from .sbp import SBPError, SBP_ESTATE
         s = ctx.solver
-        try:
-            # the forward run's checkpoints, if the solver was not used since
+        if s.checkpoint_id() == ctx.ck_id:
+            # the solver still holds this forward run's checkpoints
             g = s.gradient_from_checkpoints(grad_traces)
-        except SBPError as e:
-            if e.code != SBP_ESTATE:
-                raise
+        else:
+            # another run (e.g. a second forward pass) replaced them
             s.set_material(*_cp_cs(*ctx.mat))
             s.set_state(ctx.Q0, 0.0)
             s.record(ctx.receivers, ctx.nsteps)

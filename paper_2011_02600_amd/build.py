@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsbp.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["closure.cpp", "api.cpp", "kernels.hip", "adjoint.hip", "nn.hip"]
+SOURCES = ["closure.cpp", "host_math.cpp", "api.cpp", "kernels.hip", "adjoint.hip", "nn.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # packed FP32 instructions are disabled for all device code

@@ -15,6 +15,7 @@
 #include "../../include/sbp.h"
 #include "internal.hpp"
 #include "adjoint.hpp"
+#include "host_math.hpp"
 #include "kernels.hpp"
 
 using namespace sbp;
@@ -58,14 +59,14 @@ constexpr int kMaxGroups = 12;  // six orders x two tile heights
 
 constexpr int kMaxPart = 1024;
 constexpr double kPi = 3.14159265358979323846;
+// sbp_step: the source-time table is uploaded for kTabSteps steps at a time,
+// into one of kTabParts parts (pinned host staging, device copy)
+constexpr int kTabSteps = 512;
+constexpr int kTabParts = 4;
 
 std::size_t align256(std::size_t b) { return (b + 255) & ~std::size_t(255); }
 
-struct Geometry {
-  int nq, nr, ns;
-  std::size_t n;
-  std::size_t idx(int i, int j, int k) const { return ((std::size_t)k * nr + j) * nq + i; }
-};
+using Geometry = Grid3;
 
 struct Src {
   int i0, j0, k0;
@@ -115,12 +116,31 @@ struct sbp_ctx {
   double prof_stage_ms = 0.0, prof_edge_ms = 0.0;
   long long prof_n = 0;
   // checkpoints of the last sbp_step_checkpointed (valid until the state,
-  // the medium or the sources change)
+  // the medium, the sources or the receivers change); ck_id names them
   bool ck_valid = false;
   const char* ck_ws = nullptr;
   int ck_nsteps = 0, ck_every = 0;
   double ck_dt = 0.0, ck_t0 = 0.0;
   long long ck_steps = 0;
+  long long ck_id = 0, ck_next = 0;
+  // node coordinates (host, 3 grid functions), for sbp_add_source_at
+  std::vector<double> X;
+  // source-time tables of sbp_step: pinned host staging parts, the event of
+  // each part's last upload, the next part to use
+  char* tab_host = nullptr;
+  hipEvent_t tab_ev[kTabParts] = {};
+  bool tab_used[kTabParts] = {};
+  int tab_next = 0;
+  std::size_t off_clock = 0, off_gtab = 0, tab_part_bytes = 0;
+  // graphs of one step (index: starting ping-pong parity), captured on a
+  // private stream and launched on the handle's stream; valid while the
+  // launch settings (gen) and dt are those they were captured with
+  bool graphs = true;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gx[2] = {nullptr, nullptr};
+  long long gx_gen[2] = {-1, -1};
+  double gx_dt[2] = {0.0, 0.0};
+  long long gen = 0;  // bumped by every change of what the step's launches bake in
 };
 
 namespace {
@@ -217,6 +237,9 @@ void layout(sbp_ctx* h) {
   h->off_bounds = take((std::size_t)(g.nq + g.nr + g.ns + 16) * sizeof(int));
   h->off_tab = take((std::size_t)kClosureTab * kMaxM * kMaxCols * es);
   h->off_batch = take(batch_region_bytes());
+  h->tab_part_bytes = align256((std::size_t)kTabSteps * 5 * kMaxSources * es);
+  h->off_clock = take(sizeof(StepClock));
+  h->off_gtab = take(kTabParts * h->tab_part_bytes);
   h->total = o;
 }
 
@@ -266,49 +289,6 @@ int copy_out(sbp_ctx* h, void* dst, const char* src, int nf, hipMemcpyKind kind)
   return SBP_OK;
 }
 
-// ---- one-dimensional SBP operators on the host (double) ----------------------
-// kind 0: D+, 1: D-, 2: D0 = (D+ + D-)/2, applied along axis ax (0 q, 1 r, 2 s)
-void apply_axis(const Closure& c, const Geometry& g, const double* in, double* out, int ax, int kind) {
-  const int N = ax == 0 ? g.nq : (ax == 1 ? g.nr : g.ns);
-  const std::size_t stride = ax == 0 ? 1 : (ax == 1 ? (std::size_t)g.nq : (std::size_t)g.nq * g.nr);
-  const double ih = N - 1;
-  const int R = c.r, Q = c.q, m = c.m, nt = R + Q + 1;
-  // iterate over all lines along ax
-  const int n1 = ax == 0 ? g.nr : g.nq;
-  const int n2 = ax == 2 ? g.nr : g.ns;
-  for (int b = 0; b < n2; ++b) {
-    for (int a = 0; a < n1; ++a) {
-      std::size_t base;
-      if (ax == 0) base = g.idx(0, a, b);
-      else if (ax == 1) base = g.idx(a, 0, b);
-      else base = g.idx(a, b, 0);
-      const double* f = in + base;
-      double* o = out + base;
-      for (int i = 0; i < N; ++i) {
-        double vp = 0, vm = 0;
-        if (i >= m && i < N - m) {
-          for (int s = 0; s < nt; ++s) {
-            vp += c.alpha[s] * f[(std::size_t)(i - R + s) * stride];
-            vm -= c.alpha[s] * f[(std::size_t)(i + R - s) * stride];
-          }
-        } else if (i < m) {
-          for (int cc = 0; cc < c.ncol; ++cc) {
-            vp += c.dp[i][cc] * f[(std::size_t)cc * stride];
-            vm += c.dm[i][cc] * f[(std::size_t)cc * stride];
-          }
-        } else {
-          const int row = N - 1 - i;
-          for (int cc = 0; cc < c.ncol; ++cc) {
-            vp -= c.dm[row][cc] * f[(std::size_t)(N - 1 - cc) * stride];
-            vm -= c.dp[row][cc] * f[(std::size_t)(N - 1 - cc) * stride];
-          }
-        }
-        o[(std::size_t)i * stride] = ih * (kind == 0 ? vp : (kind == 1 ? vm : 0.5 * (vp + vm)));
-      }
-    }
-  }
-}
-
 template <typename T>
 int upload_field(sbp_ctx* h, std::size_t off, const double* src) {
   const Geometry& g = h->g;
@@ -337,48 +317,32 @@ int upload_vec(sbp_ctx* h, std::size_t off, const std::vector<double>& src) {
   return h->dtype == SBP_F32 ? upload_raw<float>(h, off, src) : upload_raw<double>(h, off, src);
 }
 
-// Metric terms (Sec. 2.2): x_xi = D0_xi x, J = det, and the conservative
-// cofactor form M[xi][c] = D-_zeta(e D0_eta d) - D-_eta(e D0_zeta d) with
-// (xi, eta, zeta), (c, d, e) cyclic.  Uploads M and keeps J and face M.
+// Metric terms (Sec. 2.2, computed by metric_terms on the host): uploads M,
+// keeps J, the face values of M and the node coordinates.
 int compute_metrics(sbp_ctx* h, const double* xyz) {
   const Geometry& g = h->g;
   const std::size_t n = g.n;
-  std::vector<double> X(3 * n);
+  h->X.assign(3 * n, 0.0);
   if (xyz) {
-    std::memcpy(X.data(), xyz, 3 * n * sizeof(double));
+    std::memcpy(h->X.data(), xyz, 3 * n * sizeof(double));
   } else {
     for (int k = 0; k < g.ns; ++k)
       for (int j = 0; j < g.nr; ++j)
         for (int i = 0; i < g.nq; ++i) {
           const std::size_t o = g.idx(i, j, k);
-          X[o] = (double)i / (g.nq - 1);
-          X[n + o] = (double)j / (g.nr - 1);
-          X[2 * n + o] = (double)k / (g.ns - 1);
+          h->X[o] = (double)i / (g.nq - 1);
+          h->X[n + o] = (double)j / (g.nr - 1);
+          h->X[2 * n + o] = (double)k / (g.ns - 1);
         }
   }
-  std::vector<double> d(9 * n);  // d[3 c + xi] = D0_xi x_c
-  for (int c = 0; c < 3; ++c)
-    for (int xi = 0; xi < 3; ++xi) apply_axis(h->cl, g, X.data() + c * n, d.data() + (3 * c + xi) * n, xi, 2);
   h->J.assign(n, 0.0);
-  for (std::size_t o = 0; o < n; ++o) {
-    const double xq = d[0 * n + o], xr = d[1 * n + o], xs = d[2 * n + o];
-    const double yq = d[3 * n + o], yr = d[4 * n + o], ys = d[5 * n + o];
-    const double zq = d[6 * n + o], zr = d[7 * n + o], zs = d[8 * n + o];
-    const double J = xq * (yr * zs - zr * ys) - yq * (xr * zs - zr * xs) + zq * (xr * ys - yr * xs);
-    if (!(J > 0)) return fail(SBP_EINVAL, "non-positive Jacobian at node %zu", o);
-    h->J[o] = J;
-  }
-  std::vector<double> tmp(n), t1(n), t2(n);
-  for (int xi = 0; xi < 3; ++xi) {
-    const int eta = (xi + 1) % 3, zeta = (xi + 2) % 3;
+  std::vector<double> M(9 * n);
+  const long long bad = metric_terms(h->cl, g, h->X.data(), h->J.data(), M.data());
+  if (bad >= 0) return fail(SBP_EINVAL, "non-positive Jacobian at node %lld", bad);
+  for (int xi = 0; xi < 3; ++xi)
     for (int c = 0; c < 3; ++c) {
-      const int dd = (c + 1) % 3, e = (c + 2) % 3;
-      for (std::size_t o = 0; o < n; ++o) tmp[o] = X[e * n + o] * d[(3 * dd + eta) * n + o];
-      apply_axis(h->cl, g, tmp.data(), t1.data(), zeta, 1);
-      for (std::size_t o = 0; o < n; ++o) tmp[o] = X[e * n + o] * d[(3 * dd + zeta) * n + o];
-      apply_axis(h->cl, g, tmp.data(), t2.data(), eta, 1);
-      for (std::size_t o = 0; o < n; ++o) t1[o] -= t2[o];
-      int rc = upload(h, h->off_coef + (std::size_t)(3 * xi + c) * h->field * h->esize, t1.data());
+      const double* t1 = M.data() + (std::size_t)(3 * xi + c) * n;
+      int rc = upload(h, h->off_coef + (std::size_t)(3 * xi + c) * h->field * h->esize, t1);
       if (rc) return rc;
       // keep the face values of M[xi][.] for the penalties of faces 2 xi, 2 xi + 1
       for (int side = 0; side < 2; ++side) {
@@ -401,7 +365,6 @@ int compute_metrics(sbp_ctx* h, const double* xyz) {
         }
       }
     }
-  }
   return SBP_OK;
 }
 
@@ -494,6 +457,7 @@ int prepare_bounds(sbp_ctx* h) {
                         h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   h->bounds_dirty = false;
+  ++h->gen;
   return SBP_OK;
 }
 
@@ -562,6 +526,8 @@ SourceArgs<T> source_args(sbp_ctx* h, int k, double dt, double tstage, bool rhs_
     s.k0[i] = h->src[i].k0;
     s.gdt[i] = (T)((rhs_only ? 1.0 : dt) * stf_value(h->src[i], tstage));
   }
+  s.clock = nullptr;
+  s.stage = k;
   return s;
 }
 
@@ -582,16 +548,23 @@ StageArgs<T> stage_entry(sbp_ctx* h, const StageArgs<T>& a, int k, int c, double
   return b;
 }
 
+// One Runge-Kutta stage (or the right-hand side alone) on stream st: the
+// stage kernel, the edge kernel, the point sources (dt * g from the clock's
+// table when clock is not null, else evaluated here at tstage).  With
+// profiling on (only on the handle's own stream) the stage and edge kernels
+// are bracketed by events and the host waits for them.
 template <typename T>
-int run_stage(sbp_ctx* h, StageArgs<T>& a, int k, double dt, double tstage, bool rhs_only, T* qin, T* qout) {
+int run_stage(sbp_ctx* h, StageArgs<T>& a, int k, double dt, double tstage, bool rhs_only, T* qin, T* qout,
+              hipStream_t st, const StepClock* clock) {
   const int c = qin == (T*)(h->ws + h->off_qb) ? 1 : 0;
   a = stage_entry<T>(h, a, k, c, dt, rhs_only);
-  if (h->prof) HIPCHK(hipEventRecord(h->ev[0], h->stream));
-  HIPCHK(launch_stage<T>(h->order, h->ty, a, h->stream));
-  if (h->prof) HIPCHK(hipEventRecord(h->ev[1], h->stream));
-  if (h->ex || h->ey) HIPCHK(launch_edge<T>(h->order, a, h->stream));
-  if (h->prof) {
-    HIPCHK(hipEventRecord(h->ev[2], h->stream));
+  const bool prof = h->prof && st == h->stream;
+  if (prof) HIPCHK(hipEventRecord(h->ev[0], st));
+  HIPCHK(launch_stage<T>(h->order, h->ty, a, st));
+  if (prof) HIPCHK(hipEventRecord(h->ev[1], st));
+  if (h->ex || h->ey) HIPCHK(launch_edge<T>(h->order, a, st));
+  if (prof) {
+    HIPCHK(hipEventRecord(h->ev[2], st));
     HIPCHK(hipEventSynchronize(h->ev[2]));
     float t01 = 0.f, t12 = 0.f;
     HIPCHK(hipEventElapsedTime(&t01, h->ev[0], h->ev[1]));
@@ -601,36 +574,111 @@ int run_stage(sbp_ctx* h, StageArgs<T>& a, int k, double dt, double tstage, bool
     ++h->prof_n;
   }
   if (!h->src.empty()) {
-    const SourceArgs<T> s = source_args<T>(h, k, dt, tstage, rhs_only, qout);
-    HIPCHK(launch_source<T>(s, (int)h->src.size(), h->stream));
+    SourceArgs<T> s = source_args<T>(h, k, dt, tstage, rhs_only, qout);
+    s.clock = clock;
+    HIPCHK(launch_source<T>(s, (int)h->src.size(), st));
   }
   return SBP_OK;
 }
 
+// The launches of one step on stream st, the state starting in buffer
+// parity c (0: Q_a): five stages, the receivers, the clock tick.  Every step
+// issues the same launches; the step-dependent values (source-time factors,
+// receiver slot) come from the clock.
+template <typename T>
+int step_launches(sbp_ctx* h, StageArgs<T>& a, int c, double dt, hipStream_t st) {
+  T* qa = (T*)(h->ws + h->off_qa);
+  T* qb = (T*)(h->ws + h->off_qb);
+  StepClock* clk = (StepClock*)(h->ws + h->off_clock);
+  for (int k = 0; k < 5; ++k) {
+    int rc = run_stage<T>(h, a, k, dt, 0.0, false, c ? qb : qa, c ? qa : qb, st, clk);
+    if (rc) return rc;
+    c ^= 1;
+  }
+  if (h->nrec > 0)
+    HIPCHK(launch_record<T>(c ? qb : qa, h->field, (const long long*)(h->ws + h->off_rec), h->nrec, (T*)h->rec_out,
+                            clk, st));
+  HIPCHK(launch_clock_tick(clk, st));
+  return SBP_OK;
+}
+
+// Captures step_launches for starting parity c into an executable graph
+// (on the handle's private capture stream).
+template <typename T>
+int capture_step(sbp_ctx* h, StageArgs<T>& a, int c, double dt) {
+  if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  if (h->gx[c]) {
+    (void)hipGraphExecDestroy(h->gx[c]);
+    h->gx[c] = nullptr;
+  }
+  HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+  const int rc = step_launches<T>(h, a, c, dt, h->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->cap, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(SBP_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  const hipError_t e2 = hipGraphInstantiate(&h->gx[c], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e2 != hipSuccess) {
+    h->gx[c] = nullptr;
+    return fail(SBP_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+  }
+  h->gx_gen[c] = h->gen;
+  h->gx_dt[c] = dt;
+  return SBP_OK;
+}
+
+// nsteps steps from the current state.  Per chunk of at most kTabSteps
+// steps: the source-time factors dt * g(t_n + C_k dt) of every step, stage
+// and source are evaluated on the host (double) and uploaded, the device
+// clock is set, and the steps are issued, each as one replay of the captured
+// step graph (or as eager launches with graphs off or profiling on; both
+// issue the same kernels with the same arguments).
 template <typename T>
 int do_steps(sbp_ctx* h, int nsteps, double dt) {
   int rc = prepare_bounds(h);
   if (rc) return rc;
   StageArgs<T> a = stage_args<T>(h);
-  T* qa = (T*)(h->ws + h->off_qa);
-  T* qb = (T*)(h->ws + h->off_qb);
+  StepClock* clk = (StepClock*)(h->ws + h->off_clock);
   const double t0 = h->t;
-  for (int n = 0; n < nsteps; ++n) {
-    const double tn = t0 + n * dt;
-    for (int k = 0; k < 5; ++k) {
-      T* qin = h->cur ? qb : qa;
-      T* qout = h->cur ? qa : qb;
-      rc = run_stage<T>(h, a, k, dt, tn + kRkC[k] * dt, false, qin, qout);
-      if (rc) return rc;
-      h->cur ^= 1;
+  const bool use_graph = h->graphs && !h->prof;
+  for (int n0 = 0; n0 < nsteps; n0 += kTabSteps) {
+    const int nc = std::min(kTabSteps, nsteps - n0);
+    const int part = h->tab_next;
+    h->tab_next = (part + 1) % kTabParts;
+    char* dtab = h->ws + h->off_gtab + (std::size_t)part * h->tab_part_bytes;
+    if (!h->src.empty()) {
+      // the staging part is reused once its previous upload has completed
+      if (h->tab_used[part]) HIPCHK(hipEventSynchronize(h->tab_ev[part]));
+      T* ht = (T*)(h->tab_host + (std::size_t)part * h->tab_part_bytes);
+      for (int nn = 0; nn < nc; ++nn) {
+        const double tn = t0 + (n0 + nn) * dt;
+        for (int k = 0; k < 5; ++k)
+          for (std::size_t q = 0; q < h->src.size(); ++q)
+            ht[((std::size_t)nn * 5 + k) * kMaxSources + q] = (T)(dt * stf_value(h->src[q], tn + kRkC[k] * dt));
+      }
+      HIPCHK(hipMemcpyAsync(dtab, ht, (std::size_t)nc * 5 * kMaxSources * sizeof(T), hipMemcpyHostToDevice,
+                            h->stream));
+      HIPCHK(hipEventRecord(h->tab_ev[part], h->stream));
+      h->tab_used[part] = true;
     }
-    if (h->nrec > 0) {
-      T* q = h->cur ? qb : qa;
-      T* out = (T*)h->rec_out + (std::size_t)h->rec_step * h->nrec * 3;
-      HIPCHK(launch_record<T>(q, h->field, (const long long*)(h->ws + h->off_rec), h->nrec, out, h->stream));
-      ++h->rec_step;
+    HIPCHK(launch_clock_set(clk, dtab, h->rec_step, h->stream));
+    for (int nn = 0; nn < nc; ++nn) {
+      const int c = h->cur;
+      if (use_graph) {
+        if (!h->gx[c] || h->gx_gen[c] != h->gen || h->gx_dt[c] != dt)
+          if ((rc = capture_step<T>(h, a, c, dt))) return rc;
+        HIPCHK(hipGraphLaunch(h->gx[c], h->stream));
+      } else {
+        if ((rc = step_launches<T>(h, a, c, dt, h->stream))) return rc;
+      }
+      h->cur ^= 1;  // five stages: the state ends in the other buffer
+      if (h->nrec > 0) ++h->rec_step;
+      ++h->steps;
     }
-    ++h->steps;
   }
   h->t = t0 + nsteps * dt;
   return SBP_OK;
@@ -855,7 +903,7 @@ int do_rhs(sbp_ctx* h, void* out, double t) {
   T* qb = (T*)(h->ws + h->off_qb);
   T* qin = h->cur ? qb : qa;
   T* qout = h->cur ? qa : qb;
-  rc = run_stage<T>(h, a, 0, 1.0, t, true, qin, qout);
+  rc = run_stage<T>(h, a, 0, 1.0, t, true, qin, qout, h->stream, nullptr);
   if (rc) return rc;
   return copy_out(h, out, h->ws + h->off_dq, 9, hipMemcpyDeviceToDevice);
 }
@@ -931,9 +979,10 @@ int do_autotune(sbp_ctx* h, int reps, int* best_ty, int* best_zchunk, double* be
       T* qb = (T*)(h->ws + h->off_qb);
       T* qin = h->cur ? qb : qa;
       T* qout = h->cur ? qa : qb;
-      if ((rc = run_stage<T>(h, a, 0, 1.0, h->t, true, qin, qout))) break;  // warm-up
+      if ((rc = run_stage<T>(h, a, 0, 1.0, h->t, true, qin, qout, h->stream, nullptr))) break;  // warm-up
       if (hipEventRecord(e0, h->stream) != hipSuccess) { rc = fail(SBP_EHIP, "hipEventRecord failed"); break; }
-      for (int r = 0; r < reps && rc == SBP_OK; ++r) rc = run_stage<T>(h, a, 0, 1.0, h->t, true, qin, qout);
+      for (int r = 0; r < reps && rc == SBP_OK; ++r)
+        rc = run_stage<T>(h, a, 0, 1.0, h->t, true, qin, qout, h->stream, nullptr);
       if (rc) break;
       float ms = 0.f;
       if (hipEventRecord(e1, h->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -1220,6 +1269,7 @@ int do_step_checkpointed(sbp_ctx* h, int nsteps, double dt, int every, char* adj
   }
   h->t = t0 + nsteps * dt;
   h->ck_valid = true;
+  h->ck_id = ++h->ck_next;
   h->ck_ws = adj;
   h->ck_nsteps = nsteps;
   h->ck_every = every;
@@ -1302,16 +1352,20 @@ int sbp_init_grid(sbp_handle* out, int nq, int nr, int ns, const double* xyz, in
       return rc;
     }
   }
-  // zero the state buffers and the Runge-Kutta register
+  // zero the state buffers and the Runge-Kutta register; pinned staging of
+  // the source-time tables and one event per part
   hipError_t e = hipMemsetAsync(h->ws, 0, h->off_coef, h->stream);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&h->tab_host, kTabParts * h->tab_part_bytes, hipHostMallocDefault);
+  for (int p = 0; p < kTabParts && e == hipSuccess; ++p)
+    e = hipEventCreateWithFlags(&h->tab_ev[p], hipEventDisableTiming);
   if (e != hipSuccess) {
-    delete h;
-    return fail(SBP_EHIP, "hipMemsetAsync: %s", hipGetErrorString(e));
+    sbp_destroy(h);
+    return fail(SBP_EHIP, "set-up: %s", hipGetErrorString(e));
   }
   rc = compute_metrics(h, xyz);
   if (rc) {
     std::string keep = g_err;
-    delete h;
+    sbp_destroy(h);
     g_err = keep;
     return rc;
   }
@@ -1385,27 +1439,19 @@ int sbp_add_source(sbp_handle h, const double* xi, const double* M, int stf, dou
     if (!(xi[a] >= 0.0 && xi[a] <= 1.0)) return fail(SBP_EINVAL, "source outside the block");
   const Geometry& g = h->g;
   const int w = h->width;
-  const int Ns[3] = {g.nq, g.nr, g.ns};
   int start[3];
   double d[3][kMaxSrcWidth];
   for (int ax = 0; ax < 3; ++ax) {
-    const int N = Ns[ax];
+    const int N = g.len(ax);
     const double u = xi[ax] * (N - 1);
-    int s0 = (int)std::floor(u) - w / 2 + 1;
-    s0 = std::min(std::max(s0, 0), N - w);
-    start[ax] = s0;
+    start[ax] = delta_window(N, w, u);
+    lagrange_basis(w, start[ax], u, d[ax], nullptr);
     for (int a = 0; a < w; ++a) {
-      double num = 1, den = 1;
-      for (int b = 0; b < w; ++b)
-        if (b != a) {
-          num *= u - (s0 + b);
-          den *= (double)(a - b);
-        }
-      const int node = s0 + a;
+      const int node = start[ax] + a;
       double Hw = 1.0;
       if (node < h->cl.m) Hw = h->cl.w[node];
       else if (node >= N - h->cl.m) Hw = h->cl.w[N - 1 - node];
-      d[ax][a] = (num / den) / (Hw / (N - 1));
+      d[ax][a] /= Hw / (N - 1);
     }
   }
   const std::size_t per = (std::size_t)kMaxSrcWidth * kMaxSrcWidth * kMaxSrcWidth * 6;
@@ -1429,13 +1475,32 @@ int sbp_add_source(sbp_handle h, const double* xi, const double* M, int stf, dou
   s.param = param;
   s.t0 = t0;
   h->src.push_back(s);
+  ++h->gen;
   return SBP_OK;
+}
+
+int sbp_locate(sbp_handle h, const double* x, double* xi) {
+  if (!h || !x || !xi) return fail(SBP_EINVAL, "NULL argument");
+  double res = 0.0;
+  const int r = locate_point(h->g, h->X.data(), h->width, x, xi, &res);
+  if (r == 1) return fail(SBP_EINVAL, "point (%g, %g, %g) lies outside the block", x[0], x[1], x[2]);
+  if (r != 0) return fail(SBP_EINVAL, "the map could not be inverted at (%g, %g, %g)", x[0], x[1], x[2]);
+  return SBP_OK;
+}
+
+int sbp_add_source_at(sbp_handle h, const double* x, const double* M, int stf, double param, double t0) {
+  if (!h || !x || !M) return fail(SBP_EINVAL, "NULL argument");
+  double xi[3];
+  const int rc = sbp_locate(h, x, xi);
+  if (rc) return rc;
+  return sbp_add_source(h, xi, M, stf, param, t0);
 }
 
 int sbp_clear_sources(sbp_handle h) {
   if (!h) return fail(SBP_EINVAL, "NULL handle");
   h->ck_valid = false;
   h->src.clear();
+  ++h->gen;
   return SBP_OK;
 }
 
@@ -1463,6 +1528,9 @@ int sbp_get_state(sbp_handle h, void* q, int q_is_device, double* t_out) {
 int sbp_record(sbp_handle h, int nrec, const int* ijk, void* out_device, int max_steps) {
   if (!h) return fail(SBP_EINVAL, "NULL handle");
   if (nrec < 0 || nrec > kMaxRec) return fail(SBP_EINVAL, "nrec must be in [0, %d]", kMaxRec);
+  // checkpoints belong to the receivers they were taken with
+  h->ck_valid = false;
+  ++h->gen;
   if (nrec == 0) {
     h->nrec = 0;
     return SBP_OK;
@@ -1600,6 +1668,7 @@ int sbp_set_launch(sbp_handle h, int ty, int zchunk) {
   h->ty = ty;
   h->zchunk = zchunk;
   h->bounds_dirty = true;
+  ++h->gen;
   return SBP_OK;
 }
 
@@ -1607,6 +1676,34 @@ int sbp_set_addressing(sbp_handle h, int plain) {
   if (!h) return fail(SBP_EINVAL, "NULL handle");
   if (plain != 0 && plain != 1) return fail(SBP_EINVAL, "plain must be 0 or 1");
   h->plain = plain == 1;
+  ++h->gen;
+  return SBP_OK;
+}
+
+int sbp_set_graphs(sbp_handle h, int on) {
+  if (!h) return fail(SBP_EINVAL, "NULL handle");
+  if (on != 0 && on != 1) return fail(SBP_EINVAL, "on must be 0 or 1");
+  h->graphs = on == 1;
+  return SBP_OK;
+}
+
+int sbp_fill_scratch(sbp_handle h, double value) {
+  if (!h) return fail(SBP_EINVAL, "NULL handle");
+  char* other = h->ws + (h->cur ? h->off_qa : h->off_qb);
+  char* dq = h->ws + h->off_dq;
+  if (h->dtype == SBP_F32) {
+    HIPCHK(launch_fill<float>((float*)other, 9 * h->field, (float)value, h->stream));
+    HIPCHK(launch_fill<float>((float*)dq, 9 * h->field, (float)value, h->stream));
+  } else {
+    HIPCHK(launch_fill<double>((double*)other, 9 * h->field, value, h->stream));
+    HIPCHK(launch_fill<double>((double*)dq, 9 * h->field, value, h->stream));
+  }
+  return SBP_OK;
+}
+
+int sbp_checkpoint_id(sbp_handle h, long long* id) {
+  if (!h || !id) return fail(SBP_EINVAL, "NULL argument");
+  *id = h->ck_valid ? h->ck_id : 0;
   return SBP_OK;
 }
 
@@ -1650,9 +1747,17 @@ int sbp_profile(sbp_handle h, double* stage_ms, double* edge_ms, long long* nsta
 }
 
 int sbp_destroy(sbp_handle h) {
-  if (h)
-    for (int e = 0; e < 3; ++e)
-      if (h->ev[e]) (void)hipEventDestroy(h->ev[e]);
+  if (!h) return SBP_OK;
+  // work still queued may read the staging buffer and the graphs
+  if (h->tab_host || h->gx[0] || h->gx[1]) (void)hipStreamSynchronize(h->stream);
+  for (int e = 0; e < 3; ++e)
+    if (h->ev[e]) (void)hipEventDestroy(h->ev[e]);
+  for (int p = 0; p < kTabParts; ++p)
+    if (h->tab_ev[p]) (void)hipEventDestroy(h->tab_ev[p]);
+  for (int c = 0; c < 2; ++c)
+    if (h->gx[c]) (void)hipGraphExecDestroy(h->gx[c]);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
+  if (h->tab_host) (void)hipHostFree(h->tab_host);
   delete h;
   return SBP_OK;
 }

@@ -1052,20 +1052,24 @@ __global__ __launch_bounds__(64 * KZ) void edge_kernel_batch(const BatchArgs<T> 
 }
 
 // ---------------------------------------------------------------------------
-// point sources: dQ += gdt * w M, Q_out += Bk * gdt * w M on the source stencil
+// point sources: dQ += gdt * w M, Q_out += Bk * gdt * w M on the source stencil.
+// One block per source; the stencils of two sources may overlap, so the
+// updates are atomic additions.
 template <typename T>
 __device__ __forceinline__ void source_body(const SourceArgs<T>& S, const int s) {
   const int w = S.width;
   const int n = w * w * w;
+  const T gdt = S.clock ? static_cast<const T*>(S.clock->gtab)[((std::size_t)S.clock->step * 5 + S.stage) * kMaxSources + s]
+                        : S.gdt[s];
   for (int t = threadIdx.x; t < n; t += blockDim.x) {
     const int a = t % w, b = (t / w) % w, c = t / (w * w);
     const std::size_t o = (std::size_t)S.nm(S.i0[s] + a, S.j0[s] + b, S.k0[s] + c);
     const T* wm = S.wm + ((std::size_t)s * kMaxSrcWidth * kMaxSrcWidth * kMaxSrcWidth + t) * 6;
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-      const T add = S.gdt[s] * wm[f];
-      S.dq[(3 + f) * S.field + o] += add;
-      if (S.qout) S.qout[(3 + f) * S.field + o] += S.Bk * add;
+      const T add = gdt * wm[f];
+      atomicAdd(&S.dq[(3 + f) * S.field + o], add);
+      if (S.qout) atomicAdd(&S.qout[(3 + f) * S.field + o], S.Bk * add);
     }
   }
 }
@@ -1096,16 +1100,26 @@ __global__ void record_kernel_batch(const RecordBatch<T> B) {
   for (int c = 0; c < 3; ++c) R.out[(std::size_t)r * 3 + c] = R.q[c * R.field + o];
 }
 
-// receivers: out[(step * nrec + r) * 3 + c] = v_c(node_r)
+// receivers: out[(slot * nrec + r) * 3 + c] = v_c(node_r), slot = the clock's
+// receiver slot of the current step (or 0 without a clock: out is the slot)
 template <typename T>
 __global__ void record_kernel(const T* __restrict__ q, std::size_t field, const long long* __restrict__ off,
-                              int nrec, T* __restrict__ out) {
+                              int nrec, T* __restrict__ out, const StepClock* __restrict__ clock) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nrec) return;
   const long long o = off[r];
+  const std::size_t slot = clock ? (std::size_t)(clock->rec0 + clock->step) : 0;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) out[(std::size_t)r * 3 + c] = q[c * field + o];
+  for (int c = 0; c < 3; ++c) out[(slot * nrec + r) * 3 + c] = q[c * field + o];
 }
+
+__global__ void clock_set_kernel(StepClock* c, const void* gtab, long long rec0) {
+  c->gtab = gtab;
+  c->rec0 = rec0;
+  c->step = 0;
+}
+
+__global__ void clock_tick_kernel(StepClock* c) { c->step += 1; }
 
 // energy: partial sums of 1/2 H J (rho |v|^2 + sigma^T C^{-1} sigma) per block
 template <typename T>
@@ -1291,8 +1305,18 @@ hipError_t launch_source(const SourceArgs<T>& s, int nsrc, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_record(const T* q, std::size_t field, const long long* off, int nrec, T* out,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(record_kernel<T>, dim3((nrec + 255) / 256), dim3(256), 0, st, q, field, off, nrec, out);
+                         const StepClock* clock, hipStream_t st) {
+  hipLaunchKernelGGL(record_kernel<T>, dim3((nrec + 255) / 256), dim3(256), 0, st, q, field, off, nrec, out, clock);
+  return hipGetLastError();
+}
+
+hipError_t launch_clock_set(StepClock* c, const void* gtab, long long rec0, hipStream_t st) {
+  hipLaunchKernelGGL(clock_set_kernel, dim3(1), dim3(1), 0, st, c, gtab, rec0);
+  return hipGetLastError();
+}
+
+hipError_t launch_clock_tick(StepClock* c, hipStream_t st) {
+  hipLaunchKernelGGL(clock_tick_kernel, dim3(1), dim3(1), 0, st, c);
   return hipGetLastError();
 }
 
@@ -1318,9 +1342,10 @@ template hipError_t launch_record_batch<float>(const RecordBatch<float>&, hipStr
 template hipError_t launch_record_batch<double>(const RecordBatch<double>&, hipStream_t);
 template hipError_t launch_source<float>(const SourceArgs<float>&, int, hipStream_t);
 template hipError_t launch_source<double>(const SourceArgs<double>&, int, hipStream_t);
-template hipError_t launch_record<float>(const float*, std::size_t, const long long*, int, float*, hipStream_t);
+template hipError_t launch_record<float>(const float*, std::size_t, const long long*, int, float*,
+                                         const StepClock*, hipStream_t);
 template hipError_t launch_record<double>(const double*, std::size_t, const long long*, int, double*,
-                                          hipStream_t);
+                                          const StepClock*, hipStream_t);
 template hipError_t launch_energy<float>(const EnergyArgs<float>&, int, hipStream_t);
 template hipError_t launch_energy<double>(const EnergyArgs<double>&, int, hipStream_t);
 

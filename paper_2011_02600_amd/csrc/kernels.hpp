@@ -40,6 +40,20 @@ struct StageArgs {
 
 constexpr int kClosureTab = 4;
 
+// Device-side clock of a run of steps: the steps of one sbp_step call are
+// issued chunk by chunk; per chunk a table of dt * g(t_stage) values
+// ([step][stage][source], handle dtype) is uploaded and the clock is set to
+// (table, first receiver slot, step 0); every step ends with a kernel that
+// advances `step`.  Kernels that depend on the step read it here, so the
+// launches of one step are the same for every step (and can be replayed
+// from a captured graph).
+struct StepClock {
+  const void* gtab;
+  long long rec0;
+  int step;
+  int pad;
+};
+
 template <typename T>
 struct SourceArgs {
   T* dq;
@@ -49,8 +63,10 @@ struct SourceArgs {
   std::size_t plane, field;
   int px, width;
   int i0[kMaxSources], j0[kMaxSources], k0[kMaxSources];
-  T gdt[kMaxSources];  // dt * g(t_stage) per source
+  T gdt[kMaxSources];  // dt * g(t_stage) per source (used when clock is null)
   T Bk;
+  const StepClock* clock;  // non-null: dt * g from the clock's table
+  int stage;               // Runge-Kutta stage (index into the clock's table)
 };
 
 template <typename T>
@@ -114,7 +130,9 @@ template <typename T>
 hipError_t launch_source(const SourceArgs<T>& s, int nsrc, hipStream_t st);
 template <typename T>
 hipError_t launch_record(const T* q, std::size_t field, const long long* off, int nrec, T* out,
-                         hipStream_t st);
+                         const StepClock* clock, hipStream_t st);
+hipError_t launch_clock_set(StepClock* c, const void* gtab, long long rec0, hipStream_t st);
+hipError_t launch_clock_tick(StepClock* c, hipStream_t st);
 template <typename T>
 hipError_t launch_energy(const EnergyArgs<T>& e, int nblocks, hipStream_t st);
 

@@ -44,6 +44,11 @@ def lib():
                               c_void_p, c_size_t, c_void_p],
             "sbp_set_material": [c_void_p, c_void_p, c_void_p, c_void_p],
             "sbp_add_source": [c_void_p, c_void_p, c_void_p, c_int, c_double, c_double],
+            "sbp_add_source_at": [c_void_p, c_void_p, c_void_p, c_int, c_double, c_double],
+            "sbp_locate": [c_void_p, c_void_p, c_void_p],
+            "sbp_set_graphs": [c_void_p, c_int],
+            "sbp_checkpoint_id": [c_void_p, P(ctypes.c_longlong)],
+            "sbp_fill_scratch": [c_void_p, c_double],
             "sbp_clear_sources": [c_void_p],
             "sbp_set_state": [c_void_p, c_void_p, c_int, c_double],
             "sbp_get_state": [c_void_p, c_void_p, c_int, P(c_double)],
@@ -115,6 +120,33 @@ def sbp_add_source(h, xi, M, stf, param, t0):
     x = _host_f64(xi, 3)
     m = _host_f64(M, 6)
     _check(lib().sbp_add_source(h, x.ctypes.data, m.ctypes.data, stf, float(param), float(t0)))
+
+
+def sbp_add_source_at(h, x, M, stf, param, t0):
+    p = _host_f64(x, 3)
+    m = _host_f64(M, 6)
+    _check(lib().sbp_add_source_at(h, p.ctypes.data, m.ctypes.data, stf, float(param), float(t0)))
+
+
+def sbp_locate(h, x):
+    p = _host_f64(x, 3)
+    xi = np.zeros(3)
+    _check(lib().sbp_locate(h, p.ctypes.data, xi.ctypes.data))
+    return xi
+
+
+def sbp_set_graphs(h, on):
+    _check(lib().sbp_set_graphs(h, 1 if on else 0))
+
+
+def sbp_fill_scratch(h, value):
+    _check(lib().sbp_fill_scratch(h, float(value)))
+
+
+def sbp_checkpoint_id(h):
+    n = ctypes.c_longlong(0)
+    _check(lib().sbp_checkpoint_id(h, ctypes.byref(n)))
+    return n.value
 
 
 def sbp_clear_sources(h):
@@ -269,6 +301,21 @@ class Solver:
 
     def add_source(self, xi, M, stf=SBP_STF_RICKER, param=2.0, t0=0.0):
         sbp_add_source(self.h, xi, M, stf, param, t0)
+
+    def add_source_at(self, x, M, stf=SBP_STF_RICKER, param=2.0, t0=0.0):
+        sbp_add_source_at(self.h, x, M, stf, param, t0)
+
+    def locate(self, x):
+        return sbp_locate(self.h, x)
+
+    def set_graphs(self, on=True):
+        sbp_set_graphs(self.h, on)
+
+    def fill_scratch(self, value):
+        sbp_fill_scratch(self.h, value)
+
+    def checkpoint_id(self):
+        return sbp_checkpoint_id(self.h)
 
     def set_state(self, Q, t=0.0):
         torch = self.torch

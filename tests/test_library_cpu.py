@@ -71,20 +71,21 @@ def test_field_size_limit():
 def test_init_rejects_bad_arguments_before_device_use():
     g_ok = np.zeros(6)
     fake = 256  # never dereferenced: validation fails first
+    # (arguments, expected code, a word of the expected message)
     cases = [
-        dict(gamma=np.array([0, 0, 0, 0, 0, 1.5])),
-        dict(gamma=np.array([np.nan, 0, 0, 0, 0, 0])),
-        dict(sat=7),
-        dict(ws=0),
-        dict(ws=fake + 8),  # misaligned
-        dict(nbytes=10),
+        (dict(gamma=np.array([0, 0, 0, 0, 0, 1.5])), sbp.SBP_EINVAL, "gamma[5]"),
+        (dict(gamma=np.array([np.nan, 0, 0, 0, 0, 0])), sbp.SBP_EINVAL, "gamma[0]"),
+        (dict(sat=7), sbp.SBP_EINVAL, "sat_variant"),
+        (dict(ws=0), sbp.SBP_EINVAL, "workspace is NULL"),
+        (dict(ws=fake + 8), sbp.SBP_EINVAL, "aligned"),  # misaligned
+        (dict(nbytes=10), sbp.SBP_ENOMEM, "too small"),
     ]
-    for c in cases:
+    for c, code, word in cases:
         with pytest.raises(sbp.SBPError) as e:
             sbp.sbp_init_grid(13, 13, 13, None, 4, sbp.SBP_F64, c.get("gamma", g_ok), c.get("sat", 0),
                               c.get("ws", fake), c.get("nbytes", 1 << 40), None)
-        assert e.value.code in (sbp.SBP_EINVAL, sbp.SBP_ENOMEM)
-    assert "gamma" in sbp.lib().sbp_last_error().decode() or True
+        assert e.value.code == code, (c, e.value)
+        assert word in str(e.value), (c, str(e.value))
 
 
 @pytest.mark.parametrize("header", HEADERS)

@@ -153,3 +153,63 @@ def test_node_by_node_rhs_equals_whole_array(order):
     got = E.rhs_at(blk, Q, nodes, 0.07, gamma, sources=[src])
     want = np.array([full[:, k, j, i] for i, j, k in nodes])
     assert np.abs(got - want).max() <= 1e-12 * np.abs(full).max()
+
+
+def _poly_map(U, V, Z):
+    """A curvilinear map polynomial of degree <= 3 in each reference
+    coordinate (exactly reproduced by Lagrange interpolation over 4 or more
+    nodes per axis)."""
+    x = U + 0.06 * U ** 2 * V - 0.03 * V * Z ** 3
+    y = V + 0.05 * V * Z ** 2 + 0.02 * U ** 3
+    z = Z + 0.04 * U * V * Z - 0.05 * Z ** 2 * V
+    return np.stack([x, y, z])
+
+
+@pytest.mark.parametrize("order", [2, 4, 6])
+def test_locate_inverts_polynomial_map_exactly(order):
+    """On a map that the interpolant reproduces exactly (degree < 2(p+1) per
+    axis, p = order // 2 >= 1), locating X(xi*) returns xi* (random points,
+    points in the boundary closures and on faces, corners)."""
+    nq, nr, ns = 17, 15, 19
+    ref = W.unit_cube(nq, nr, ns)
+    X = _poly_map(ref[0], ref[1], ref[2])
+    blk = E.Block(X, order)
+    rng = np.random.default_rng(order)
+    pts = [tuple(rng.uniform(0, 1, 3)) for _ in range(6)]
+    pts += [(0.0, 0.3, 0.7), (1.0, 1.0, 0.0), (0.02, 0.97, 0.5), (0.51, 0.0, 1.0)]
+    for xs in pts:
+        x = _poly_map(*[np.array(v) for v in xs])
+        got = E.locate(blk, x)
+        assert np.allclose(got, xs, atol=1e-11, rtol=0), (xs, got)
+
+
+def test_locate_nodes_and_outside():
+    """A node's coordinates give that node's reference position; a point
+    beyond a face is rejected."""
+    xyz = W.warped_mesh(13, 14, 12, seed=5)
+    blk = E.Block(xyz, 4)
+    for (k, j, i) in [(0, 0, 0), (11, 13, 12), (4, 7, 2), (6, 0, 9)]:
+        got = E.locate(blk, xyz[:, k, j, i])
+        assert np.allclose(got, (i / 12, j / 13, k / 11), atol=1e-12)
+    with pytest.raises(ValueError):
+        E.locate(blk, xyz[:, 5, 5, 0] - np.array([0.05, 0.0, 0.0]))
+
+
+def test_locate_topography_map():
+    """On the transfinite topography mesh x = xi L, y = eta L, z = -D +
+    zeta (z_top + D), locating a point returns xi and eta exactly (x and y
+    are linear in them) and zeta to within the interpolation error of the
+    surface (closed form zeta = (z + D) / (z_top + D))."""
+    wl = W.topo_layer(nq=65, nr=65, ns=49)
+    blk = E.Block(wl["xyz"], 6)
+    L, D = 12.8, 9.6
+    rng = np.random.default_rng(2)
+    _, ztop = W.topo_mesh(5, 5, 5)
+    for _ in range(4):
+        xs, ys = rng.uniform(0.1, 0.9, 2) * L
+        zt = float(ztop(np.array(xs), np.array(ys)))
+        zeta = rng.uniform(0.1, 0.9)
+        z = -D + zeta * (zt + D)
+        got = E.locate(blk, (xs, ys, z))
+        assert abs(got[0] - xs / L) < 1e-12 and abs(got[1] - ys / L) < 1e-12
+        assert abs(got[2] - zeta) < 1e-6
