@@ -373,6 +373,11 @@ def run_batched(args, W, sbp, torch, np, dev):
         print("bench: shot %d: %d^3 order %d, launch ty %d zchunk %d" % (n, sh["xyz"].shape[1], sh["order"], ty, zc),
               file=sys.stderr, flush=True)
     hs = [s.h for s in solvers]
+    # the batch's own launch shape: s-chunk length of the persistent stage
+    # launch over every shot's tiles
+    batch_L, batch_stage_ms = sbp.sbp_autotune_batch(hs, 3)
+    print("bench: batch autotune: s-chunk %d, %.3f ms per batched stage launch" % (batch_L, batch_stage_ms),
+          file=sys.stderr, flush=True)
     dts = [sh["dt"] for sh in shots]
     stream = solvers[0].stream
     points = sum(int(np.prod(sh["xyz"].shape[1:])) for sh in shots)
@@ -418,7 +423,11 @@ def run_batched(args, W, sbp, torch, np, dev):
                                "Ricker moment source, 16 surface receivers each, CFL 0.5",
                    "sizes": [int(sh["xyz"].shape[1]) for sh in shots],
                    "orders": [sh["order"] for sh in shots], "points": points,
-                   "launch": [{"ty": t, "zchunk": z} for t, z in shapes]},
+                   "launch": "one stage launch per Runge-Kutta stage over a work list of the tiles and edge blocks of "
+                             "all 32 shots (8-row tiles, s-chunk %d from the batch autotuner), steps replayed "
+                             "from captured graphs" % batch_L,
+                   "single_shot_launch": [{"ty": t, "zchunk": z} for t, z in shapes]},
+        "batch_stage_launch_ms": round(batch_stage_ms, 4),
         "mpts_stage_per_s": round(points * 5 * steps / secs / 1e6, 1),
         "one_by_one": {"ms": round(seq_ms, 2), "shots_per_s": round(len(shots) / (seq_ms / 1e3), 3),
                        "batch_speedup": round(seq_ms / batch_ms, 3)},

@@ -192,10 +192,11 @@ int sbp_record(sbp_handle h, int nrec, const int* ijk, void* out_device, int max
  * (volume terms, penalties, sources) and is fused with the stage update
  * dQ <- A_k dQ + dt RHS, Q <- Q + B_k dQ.  Asynchronous on the stream.
  * SBP_ESTATE before sbp_set_material.
- * Each step is one replay of a HIP graph holding the step's launches (five
- * stages of stage, edge and source kernels, the receivers, a clock tick),
- * captured on first use and again whenever dt, the sources, the receivers
- * or the launch shape change.  The per-step values (the source-time factor
+ * The call's first step is issued as direct launches (five stages of
+ * stage, edge and source kernels, the receivers, a clock tick); every later
+ * step is one replay of a HIP graph holding the same launches, captured on
+ * first use and again whenever dt, the sources, the receivers or the launch
+ * shape change.  The per-step values (the source-time factor
  * dt g(t_n + C_k dt) of every stage, evaluated on the host in double, and
  * the receiver slot) are read from a device table and a device step
  * counter, uploaded / set once per 512 steps.
@@ -211,21 +212,42 @@ int sbp_set_graphs(sbp_handle h, int on);
 
 /*
  * Advance n handles (1 <= n <= 64) by nsteps steps each, handle i with step
- * dt[i] (host array of n doubles), in shared launches: per Runge-Kutta
- * stage one stage-kernel and one edge-kernel launch for all handles of the
- * same order and tile height, one launch for all their point sources, and
- * one receiver launch per step.  Each handle's state, time, step count and
- * receiver traces end up as after sbp_step(hs[i], nsteps, dt[i]).
- * All handles need the same dtype and the same stream, distinct handles and
- * a medium; the argument tables live in hs[0]'s workspace.  Each handle's
- * tile height is kept; the s-chunk length is chosen for the batch as a whole
- * (the handles' own settings are restored on return).  Synchronises the
- * stream before returning.  Results agree with separate sbp_step calls to
+ * dt[i] (host array of n doubles): batched stepping of many independent
+ * sources or media ("shots") on grids of uneven size and mixed interior
+ * orders.  Per Runge-Kutta stage one launch covers a list of the
+ * stage-kernel tiles and edge-kernel blocks of every handle, split into one
+ * segment per XCD of equal estimated cost, longest items first (block b of
+ * the launch runs item b / 8 of segment b % 8); then one launch injects
+ * every point source; per step one launch records every receiver.  In
+ * SBP_F32 each step is a replay of a graph captured for the call (even and
+ * odd steps); in SBP_F64 the same launches are issued directly.  The
+ * source-time factors come from a device table uploaded every 64 steps.
+ * Every grid uses
+ * 8-row tiles and one s-chunk length for the batch (from
+ * sbp_autotune_batch, else a cost model); the handles' own launch settings
+ * are restored on return.  With plain addressing on any handle
+ * (sbp_set_addressing), one stage and one edge launch per interior order
+ * replace the work-list launch.  Each handle's state, time, step count and
+ * receiver traces end up as after sbp_step(hs[i], nsteps, dt[i]), to
  * rounding (the batched kernels are separate instantiations of the same
- * kernel bodies).  Batched stepping of many independent sources or media
- * ("shots") on grids of uneven size.
+ * kernel bodies).  All handles need the same dtype and the same stream,
+ * distinct handles and a medium; the argument tables and the work list
+ * (at most 65536 items) live in hs[0]'s workspace.  Synchronises the
+ * stream before returning.
  */
 int sbp_step_batch(sbp_handle* hs, int n, int nsteps, const double* dt);
+
+/*
+ * Launch-shape autotuner of sbp_step_batch: times `reps` batched
+ * right-hand-side launches (the work-list launch over every handle's tiles;
+ * they write only the Runge-Kutta registers and the second state buffers,
+ * so the states are untouched) for the cost model's s-chunk length and a few
+ * others, and keeps the fastest for later sbp_step_batch calls of these
+ * handles.  Writes the chosen length and its time per launch (ms) to the
+ * outputs (each may be NULL).  Same requirements on hs as sbp_step_batch.
+ * Synchronises the stream.
+ */
+int sbp_autotune_batch(sbp_handle* hs, int n, int reps, int* zchunk, double* ms);
 
 /*
  * Evaluate the semi-discrete right-hand side dQ/dt of the current state at

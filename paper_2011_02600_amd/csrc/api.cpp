@@ -51,11 +51,13 @@ const double kRkC[5] = {0.0, 1432997174477.0 / 9575080441755.0, 2526269341429.0 
                         2006345519317.0 / 3224310063776.0, 2802321613138.0 / 2924317926251.0};
 
 constexpr int kMaxRec = 65536;
-// sbp_step_batch: at most kMaxBatch handles; per-step tables are uploaded for
-// kBatchSteps steps at a time; handles are grouped by (order, tile height)
+// sbp_step_batch: at most kMaxBatch handles and kMaxItems work items; the
+// source-time table is uploaded for kBatchTabSteps steps at a time (two
+// parts); with plain addressing the handles are grouped by interior order
 constexpr int kMaxBatch = 64;
-constexpr int kBatchSteps = 32;
-constexpr int kMaxGroups = 12;  // six orders x two tile heights
+constexpr int kBatchTabSteps = 64;
+constexpr int kMaxItems = 65536;
+constexpr int kMaxGroups = 6;  // six orders
 
 constexpr int kMaxPart = 1024;
 constexpr double kPi = 3.14159265358979323846;
@@ -136,6 +138,12 @@ struct sbp_ctx {
   // private stream and launched on the handle's stream; valid while the
   // launch settings (gen) and dt are those they were captured with
   bool graphs = true;
+  int batch_L = 0;  // s-chunk length for sbp_step_batch (0: cost model), from sbp_autotune_batch
+  // pinned staging of the batch source-time table (first handle of a batch)
+  char* btab_host = nullptr;
+  hipEvent_t btab_ev[2] = {};
+  bool btab_used[2] = {};
+  int btab_next = 0;
   hipStream_t cap = nullptr;
   hipGraphExec_t gx[2] = {nullptr, nullptr};
   long long gx_gen[2] = {-1, -1};
@@ -181,9 +189,13 @@ int check_dims(int nq, int nr, int ns, int order, int dtype) {
 }
 
 // Tables of sbp_step_batch, in the workspace of the first handle of a batch
-// (sized for double, the larger argument blocks).
+// (sized for double, the larger argument blocks): stage arguments of every
+// (stage, parity) and handle, group block prefixes (grouped launches), source
+// arguments of every (stage, parity), receiver arguments of both step
+// parities, the work list and its segments, the clock, the source-time table
+// (two parts).
 struct BatchRegion {
-  std::size_t stage, first, src, src_first, rec, rec_first, total;
+  std::size_t stage, first, src, src_first, rec, rec_first, items, seg, clock, gtab, gtab_part, total;
 };
 BatchRegion batch_region() {
   BatchRegion r{};
@@ -195,10 +207,15 @@ BatchRegion batch_region() {
   };
   r.stage = take((std::size_t)10 * kMaxBatch * sizeof(StageArgs<double>));
   r.first = take((std::size_t)2 * kMaxGroups * (kMaxBatch + 1) * sizeof(int));
-  r.src = take((std::size_t)kBatchSteps * 5 * kMaxBatch * sizeof(SourceArgs<double>));
+  r.src = take((std::size_t)10 * kMaxBatch * sizeof(SourceArgs<double>));
   r.src_first = take((std::size_t)(kMaxBatch + 1) * sizeof(int));
-  r.rec = take((std::size_t)kBatchSteps * kMaxBatch * sizeof(RecordArgs<double>));
+  r.rec = take((std::size_t)2 * kMaxBatch * sizeof(RecordArgs<double>));
   r.rec_first = take((std::size_t)(kMaxBatch + 1) * sizeof(int));
+  r.items = take((std::size_t)kMaxItems * sizeof(BatchItem));
+  r.seg = take(9 * sizeof(int));
+  r.clock = take(sizeof(StepClock));
+  r.gtab_part = align256((std::size_t)kBatchTabSteps * 5 * kMaxBatch * kMaxSources * sizeof(double));
+  r.gtab = take(2 * r.gtab_part);
   r.total = o;
   return r;
 }
@@ -634,9 +651,10 @@ int capture_step(sbp_ctx* h, StageArgs<T>& a, int c, double dt) {
 // nsteps steps from the current state.  Per chunk of at most kTabSteps
 // steps: the source-time factors dt * g(t_n + C_k dt) of every step, stage
 // and source are evaluated on the host (double) and uploaded, the device
-// clock is set, and the steps are issued, each as one replay of the captured
-// step graph (or as eager launches with graphs off or profiling on; both
-// issue the same kernels with the same arguments).
+// clock is set, and the steps are issued: the call's first step as direct
+// launches, every later one as a replay of the step graph captured from
+// those launches (all direct with graphs off or profiling on; either way the
+// same kernels with the same arguments).
 template <typename T>
 int do_steps(sbp_ctx* h, int nsteps, double dt) {
   int rc = prepare_bounds(h);
@@ -668,7 +686,9 @@ int do_steps(sbp_ctx* h, int nsteps, double dt) {
     HIPCHK(launch_clock_set(clk, dtab, h->rec_step, h->stream));
     for (int nn = 0; nn < nc; ++nn) {
       const int c = h->cur;
-      if (use_graph) {
+      // the first step of a call is issued directly, later ones replay the
+      // graph captured from the same launches
+      if (use_graph && n0 + nn > 0) {
         if (!h->gx[c] || h->gx_gen[c] != h->gen || h->gx_dt[c] != dt)
           if ((rc = capture_step<T>(h, a, c, dt))) return rc;
         HIPCHK(hipGraphLaunch(h->gx[c], h->stream));
@@ -684,213 +704,501 @@ int do_steps(sbp_ctx* h, int nsteps, double dt) {
   return SBP_OK;
 }
 
-// Several handles advanced together: the same kernels and per-grid
-// arguments as do_steps, but each launch covers the tiles of all grids of
-// one (order, tile height) group.  Results agree with do_steps to rounding
-// (the batched kernels are compiled separately).
+// ---- batched stepping (sbp_step_batch) -------------------------------------
+// Launch settings of a batch: every grid gets 8-row tiles and one s-chunk
+// length L, chosen for the batch as a whole (each grid's own automatic
+// choice assumes it has the whole GPU and cuts small grids into short
+// chunks, each paying r + q + 1 warm-up planes); the handles' own settings
+// are restored by BatchSettings' destructor.
+struct BatchSettings {
+  sbp_ctx** hs = nullptr;
+  int n = 0;
+  std::vector<int> ty, zc;
+  BatchSettings(sbp_ctx** h, int nn) : hs(h), n(nn) {
+    for (int g = 0; g < n; ++g) {
+      ty.push_back(hs[g]->ty);
+      zc.push_back(hs[g]->zchunk);
+    }
+  }
+  ~BatchSettings() {
+    for (int g = 0; g < n; ++g) {
+      hs[g]->ty = ty[g];
+      hs[g]->zchunk = zc[g];
+      hs[g]->bounds_dirty = true;
+    }
+  }
+};
+
+int device_cus() {
+  int cus = 256, dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+  }
+  return cus;
+}
+
+// the cost model's chunk length: waves of one block per compute unit times
+// the planes a block marches (its chunk plus the warm-up planes)
+int batch_cost_model_L(sbp_ctx** hs, int n) {
+  const int cus = device_cus();
+  int nsmax = 0;
+  for (int g = 0; g < n; ++g) nsmax = std::max(nsmax, hs[g]->g.ns);
+  long long best = -1;
+  int bestL = nsmax;
+  for (int L = nsmax; L >= 8; L = L * 3 / 4) {
+    long long tiles = 0, planes = 0;
+    for (int g = 0; g < n; ++g) {
+      const sbp_ctx* h = hs[g];
+      const int Lg = std::min(L, h->g.ns);
+      const int nz = (h->g.ns + Lg - 1) / Lg;
+      tiles += (long long)h->nxt * h->nyt * nz;
+      planes = std::max<long long>(planes, (h->g.ns + nz - 1) / nz + h->cl.r + h->cl.q + 1);
+    }
+    const long long cost = (tiles + cus - 1) / cus * planes;
+    if (best < 0 || cost < best) {
+      best = cost;
+      bestL = L;
+    }
+  }
+  return bestL;
+}
+
+// applies chunk length L (0: the cost model's) and 8-row tiles to every grid
+int batch_apply_L(sbp_ctx** hs, int n, int L) {
+  for (int g = 0; g < n; ++g) {
+    hs[g]->ty = 8;
+    hs[g]->zchunk = 0;
+    hs[g]->bounds_dirty = true;
+    int rc = prepare_bounds(hs[g]);  // tiles across s (nxt, nyt)
+    if (rc) return rc;
+  }
+  if (L <= 0) L = batch_cost_model_L(hs, n);
+  for (int g = 0; g < n; ++g) {
+    hs[g]->zchunk = std::min(L, hs[g]->g.ns);
+    hs[g]->bounds_dirty = true;
+    int rc = prepare_bounds(hs[g]);
+    if (rc) return rc;
+  }
+  return SBP_OK;
+}
+
+// The work list: every grid's stage tiles and edge blocks, cut into 8
+// contiguous segments of equal estimated cost (grids largest first, tiles
+// in tile order, so that neighbouring tiles share a segment and hence an
+// XCD's L2), each segment sorted longest first.
+template <typename T>
+int batch_items(sbp_ctx** hs, int n, std::vector<BatchItem>& items, std::vector<int>& seg) {
+  struct W {
+    BatchItem it;
+    long long cost;
+  };
+  std::vector<int> byn(n);
+  for (int g = 0; g < n; ++g) byn[g] = g;
+  std::stable_sort(byn.begin(), byn.end(), [&](int a, int b) { return hs[a]->g.n > hs[b]->g.n; });
+  std::vector<W> all;
+  long long total = 0;
+  for (int g : byn) {
+    sbp_ctx* h = hs[g];
+    const StageArgs<T> a = stage_args<T>(h);
+    const long long planes = (h->g.ns + h->nzc - 1) / h->nzc + h->cl.r + h->cl.q + 1;
+    for (int t = 0; t < a.ntiles; ++t) all.push_back({{g, 0, t, h->order}, planes * 64 * 8});
+    const int eb = edge_blocks(a);
+    // an edge block computes 64 x 8 points with gathers along its normal axis
+    for (int b = 0; b < eb; ++b) all.push_back({{g, 1, b, h->order}, 4 * 64 * 8});
+  }
+  if ((long long)all.size() > kMaxItems)
+    return fail(SBP_EINVAL, "batch has %zu blocks of work, more than %d", all.size(), kMaxItems);
+  for (const W& w : all) total += w.cost;
+  seg.assign(9, 0);
+  items.clear();
+  std::size_t p = 0;
+  long long acc = 0;
+  for (int x = 0; x < 8; ++x) {
+    seg[x] = (int)items.size();
+    const long long goal = total * (x + 1) / 8;
+    std::vector<W> part;
+    while (p < all.size() && (acc < goal || x == 7)) {
+      acc += all[p].cost;
+      part.push_back(all[p++]);
+    }
+    std::stable_sort(part.begin(), part.end(), [](const W& a, const W& b) { return a.cost > b.cost; });
+    for (const W& w : part) items.push_back(w.it);
+  }
+  seg[8] = (int)items.size();
+  return SBP_OK;
+}
+
+// Static tables of a batched run from the current state of each handle:
+// stage arguments (5 stages x 2 parities of the stage input), the work list
+// (one launch over it) or group prefixes (one launch per order), source arguments (clock-driven,
+// 5 stages x 2 parities), receiver arguments (2 step parities).
+template <typename T>
+struct BatchPlan {
+  bool worklist = true;  // one launch over the work list (else one per order)
+  unsigned orders = 0;   // bit o: interior order o present
+  int maxseg = 0;        // longest work-list segment
+  int ngroups = 0;
+  std::vector<int> gstart, ord, sblocks, eblocks;
+  std::vector<int> withsrc, withrec;
+  int nsrc = 0, nrec = 0;
+};
+
+template <typename T>
+int batch_upload(sbp_ctx** hs, int n, const double* dt, bool rhs_only, BatchPlan<T>& P) {
+  sbp_ctx* h0 = hs[0];
+  hipStream_t st = h0->stream;
+  const BatchRegion R = batch_region();
+  char* base = h0->ws + h0->off_batch;
+  bool buf_ok = true;
+  for (int g = 0; g < n; ++g) {
+    const StageArgs<T> a = stage_args<T>(hs[g]);
+    buf_ok = buf_ok && !a.plain && 12.0 * (double)a.field * sizeof(T) < 4294967296.0;
+    buf_ok = buf_ok && worklist_order_ok<T>(hs[g]->order);
+  }
+  P.worklist = buf_ok;
+  P.orders = 0;
+  for (int g = 0; g < n; ++g) P.orders |= 1u << hs[g]->order;
+  // stage argument tables: entry (k, P) of handle g, P the parity of the stage
+  // input relative to the handle's current buffer
+  std::vector<StageArgs<T>> sa((std::size_t)10 * kMaxBatch);
+  for (int g = 0; g < n; ++g) {
+    sbp_ctx* h = hs[g];
+    const StageArgs<T> a = stage_args<T>(h);
+    for (int k = 0; k < 5; ++k)
+      for (int p = 0; p < 2; ++p)
+        sa[(std::size_t)(k * 2 + p) * kMaxBatch + g] = stage_entry<T>(h, a, k, h->cur ^ p, dt[g], rhs_only);
+  }
+  // wait for work of an earlier call that may still read the tables
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipMemcpyAsync(base + R.stage, sa.data(), sa.size() * sizeof(StageArgs<T>), hipMemcpyHostToDevice, st));
+  if (P.worklist) {
+    std::vector<BatchItem> items;
+    std::vector<int> seg;
+    int rc = batch_items<T>(hs, n, items, seg);
+    if (rc) return rc;
+    P.maxseg = 0;
+    for (int x = 0; x < 8; ++x) P.maxseg = std::max(P.maxseg, seg[x + 1] - seg[x]);
+    HIPCHK(hipMemcpyAsync(base + R.items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(base + R.seg, seg.data(), seg.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  } else {
+    // grouped launches: the stage and edge blocks of all grids of one order
+    // per launch (block -> grid through prefix sums)
+    P.ord.resize(n);
+    for (int g = 0; g < n; ++g) P.ord[g] = g;
+    std::stable_sort(P.ord.begin(), P.ord.end(), [&](int a, int b) { return hs[a]->order < hs[b]->order; });
+    P.gstart.assign(1, 0);
+    for (int q = 1; q < n; ++q)
+      if (hs[P.ord[q]]->order != hs[P.ord[q - 1]]->order) P.gstart.push_back(q);
+    P.ngroups = (int)P.gstart.size();
+    P.gstart.push_back(n);
+    if (P.ngroups > kMaxGroups) return fail(SBP_EINVAL, "too many interior orders in a batch");
+    // the grouped kernels index the argument table in group order
+    std::vector<StageArgs<T>> sg((std::size_t)10 * kMaxBatch);
+    for (int e = 0; e < 10; ++e)
+      for (int q = 0; q < n; ++q) sg[(std::size_t)e * kMaxBatch + q] = sa[(std::size_t)e * kMaxBatch + P.ord[q]];
+    HIPCHK(hipMemcpyAsync(base + R.stage, sg.data(), sg.size() * sizeof(StageArgs<T>), hipMemcpyHostToDevice, st));
+    std::vector<int> firsts((std::size_t)2 * kMaxGroups * (kMaxBatch + 1), 0);
+    P.sblocks.assign(P.ngroups, 0);
+    P.eblocks.assign(P.ngroups, 0);
+    for (int G = 0; G < P.ngroups; ++G) {
+      int* fs = firsts.data() + (std::size_t)(2 * G) * (kMaxBatch + 1);
+      int* fe = firsts.data() + (std::size_t)(2 * G + 1) * (kMaxBatch + 1);
+      int ts = 0, te = 0;
+      for (int q = P.gstart[G]; q < P.gstart[G + 1]; ++q) {
+        const StageArgs<T> a = stage_args<T>(hs[P.ord[q]]);
+        fs[q - P.gstart[G]] = ts;
+        fe[q - P.gstart[G]] = te;
+        ts += a.ntiles;
+        te += edge_blocks(a);
+      }
+      fs[P.gstart[G + 1] - P.gstart[G]] = ts;
+      fe[P.gstart[G + 1] - P.gstart[G]] = te;
+      P.sblocks[G] = ts;
+      P.eblocks[G] = te;
+    }
+    HIPCHK(hipMemcpyAsync(base + R.first, firsts.data(), firsts.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  }
+  if (rhs_only) {
+    HIPCHK(hipStreamSynchronize(st));  // the host tables are released on return
+    return SBP_OK;
+  }
+  // sources: handles with sources, compacted; entry (k, P) of each; the
+  // source-time factor from the clock's table, row (step, k) of n x
+  // kMaxSources entries, this handle's at g * kMaxSources
+  P.withsrc.clear();
+  P.withrec.clear();
+  for (int g = 0; g < n; ++g) {
+    if (!hs[g]->src.empty()) P.withsrc.push_back(g);
+    if (hs[g]->nrec > 0) P.withrec.push_back(g);
+  }
+  const StepClock* clk = (const StepClock*)(base + R.clock);
+  std::vector<int> sfirst(P.withsrc.size() + 1, 0), rfirst(P.withrec.size() + 1, 0);
+  for (std::size_t q = 0; q < P.withsrc.size(); ++q) sfirst[q + 1] = sfirst[q] + (int)hs[P.withsrc[q]]->src.size();
+  for (std::size_t q = 0; q < P.withrec.size(); ++q) rfirst[q + 1] = rfirst[q] + hs[P.withrec[q]]->nrec;
+  P.nsrc = sfirst.back();
+  P.nrec = rfirst.back();
+  std::vector<SourceArgs<T>> stab((std::size_t)10 * kMaxBatch);
+  for (std::size_t q = 0; q < P.withsrc.size(); ++q) {
+    const int g = P.withsrc[q];
+    sbp_ctx* h = hs[g];
+    for (int k = 0; k < 5; ++k)
+      for (int p = 0; p < 2; ++p) {
+        const int c = h->cur ^ p;  // parity of the stage input
+        T* qout = (T*)(h->ws + (c ? h->off_qa : h->off_qb));
+        SourceArgs<T> sarg = source_args<T>(h, k, dt[g], 0.0, false, qout);
+        sarg.clock = clk;
+        sarg.tab_stride = n * kMaxSources;
+        sarg.tab_off = g * kMaxSources;
+        stab[(std::size_t)(k * 2 + p) * kMaxBatch + q] = sarg;
+      }
+  }
+  std::vector<RecordArgs<T>> rtab((std::size_t)2 * kMaxBatch);
+  for (std::size_t q = 0; q < P.withrec.size(); ++q) {
+    sbp_ctx* h = hs[P.withrec[q]];
+    for (int par = 0; par < 2; ++par) {
+      // state after a step of parity par: five stages flip the buffer
+      const int c = h->cur ^ (par ^ 1);
+      RecordArgs<T> r{};
+      r.q = (const T*)(h->ws + (c ? h->off_qb : h->off_qa));
+      r.field = h->field;
+      r.off = (const long long*)(h->ws + h->off_rec);
+      r.out = (T*)h->rec_out;
+      r.base = h->rec_step;
+      rtab[(std::size_t)par * kMaxBatch + q] = r;
+    }
+  }
+  HIPCHK(hipMemcpyAsync(base + R.src, stab.data(), stab.size() * sizeof(SourceArgs<T>), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(base + R.src_first, sfirst.data(), sfirst.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(base + R.rec, rtab.data(), rtab.size() * sizeof(RecordArgs<T>), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(base + R.rec_first, rfirst.data(), rfirst.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));  // the host tables are released on return
+  return SBP_OK;
+}
+
+// One batched stage launch (all grids) for argument entry e = k * 2 + P.
+template <typename T>
+int batch_stage_launch(sbp_ctx** hs, const BatchPlan<T>& P, int k, int e, hipStream_t st) {
+  sbp_ctx* h0 = hs[0];
+  const BatchRegion R = batch_region();
+  char* base = h0->ws + h0->off_batch;
+  const StageArgs<T>* dsa = (const StageArgs<T>*)(base + R.stage) + (std::size_t)e * kMaxBatch;
+  if (P.worklist) {
+    PersistArgs<T> pa{};
+    pa.args = dsa;
+    pa.items = (const BatchItem*)(base + R.items);
+    pa.seg = (const int*)(base + R.seg);
+    HIPCHK(launch_stage_worklist<T>(pa, P.orders, 8 * P.maxseg, st));
+    return SBP_OK;
+  }
+  const int* dfirst = (const int*)(base + R.first);
+  for (int G = 0; G < P.ngroups; ++G) {
+    BatchArgs<T> b{};
+    b.args = dsa + P.gstart[G];
+    b.n = P.gstart[G + 1] - P.gstart[G];
+    b.first = dfirst + (std::size_t)(2 * G) * (kMaxBatch + 1);
+    b.total = P.sblocks[G];
+    const int order = hs[P.ord[P.gstart[G]]]->order;
+    HIPCHK(launch_stage_batch<T>(order, 8, b, false, st));
+    b.first = dfirst + (std::size_t)(2 * G + 1) * (kMaxBatch + 1);
+    b.total = P.eblocks[G];
+    HIPCHK(launch_edge_batch<T>(order, b, st));
+  }
+  return SBP_OK;
+}
+
+// The launches of one batched step of parity par (0: even step of the call)
+// on stream st: per stage the batched stage launch and the sources, then the
+// receivers and the clock tick.
+template <typename T>
+int batch_step_launches(sbp_ctx** hs, const BatchPlan<T>& P, int par, hipStream_t st) {
+  sbp_ctx* h0 = hs[0];
+  const BatchRegion R = batch_region();
+  char* base = h0->ws + h0->off_batch;
+  StepClock* clk = (StepClock*)(base + R.clock);
+  for (int k = 0; k < 5; ++k) {
+    const int e = k * 2 + ((par + k) & 1);
+    int rc = batch_stage_launch<T>(hs, P, k, e, st);
+    if (rc) return rc;
+    if (P.nsrc > 0) {
+      SourceBatch<T> sb{};
+      sb.args = (const SourceArgs<T>*)(base + R.src) + (std::size_t)e * kMaxBatch;
+      sb.first = (const int*)(base + R.src_first);
+      sb.n = (int)P.withsrc.size();
+      sb.total = P.nsrc;
+      HIPCHK(launch_source_batch<T>(sb, st));
+    }
+  }
+  if (P.nrec > 0) {
+    RecordBatch<T> rb{};
+    rb.args = (const RecordArgs<T>*)(base + R.rec) + (std::size_t)par * kMaxBatch;
+    rb.first = (const int*)(base + R.rec_first);
+    rb.n = (int)P.withrec.size();
+    rb.total = P.nrec;
+    rb.clock = clk;
+    HIPCHK(launch_record_batch<T>(rb, st));
+  }
+  HIPCHK(launch_clock_tick(clk, st));
+  return SBP_OK;
+}
+
+// Several handles advanced together.  Per Runge-Kutta stage one launch
+// covers the stage tiles and edge blocks of every grid (a work list cut into
+// one segment per XCD, longest items first; with plain addressing, one stage
+// and one edge launch per interior order), then one launch injects every
+// source; per step one launch records every receiver.  In FP32 each step is
+// a replay of one of two graphs captured for the call (even and odd steps;
+// the argument tables hold both ping-pong parities); the per-step values
+// come from a device clock and a source-time table uploaded every
+// kBatchTabSteps steps.  Results agree with do_steps to rounding (the bodies
+// are the same, instantiated in another kernel).
 template <typename T>
 int do_steps_batch(sbp_ctx** hs, int n, int nsteps, const double* dt) {
   sbp_ctx* h0 = hs[0];
   hipStream_t st = h0->stream;
   const BatchRegion R = batch_region();
   char* base = h0->ws + h0->off_batch;
-  // s-chunks for the batch: every grid's own automatic choice assumes it has
-  // the whole GPU; here one chunk length L serves all grids (whatever their
-  // own setting), picked by the same wave cost model over the total work,
-  // waves x (L + warm-up)
-  std::vector<int> zsave(n);
-  for (int g = 0; g < n; ++g) {
-    zsave[g] = hs[g]->zchunk;
-    int rc = prepare_bounds(hs[g]);  // tiles across s (nxt, nyt)
-    if (rc) return rc;
+  BatchSettings keep(hs, n);
+  int rc = batch_apply_L(hs, n, h0->batch_L);
+  if (rc) return rc;
+  BatchPlan<T> P;
+  if ((rc = batch_upload<T>(hs, n, dt, false, P))) return rc;
+  if (!h0->btab_host) {
+    HIPCHK(hipHostMalloc((void**)&h0->btab_host, 2 * R.gtab_part, hipHostMallocDefault));
+    for (int p = 0; p < 2; ++p) HIPCHK(hipEventCreateWithFlags(&h0->btab_ev[p], hipEventDisableTiming));
   }
-  {
-    int cus = 256, dev = 0;
-    if (hipGetDevice(&dev) == hipSuccess) {
-      int v = 0;
-      if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
-    }
-    int nsmax = 0;
-    for (int g = 0; g < n; ++g) nsmax = std::max(nsmax, hs[g]->g.ns);
-    long long best = -1;
-    int bestL = nsmax;
-    for (int L = nsmax; L >= 8; L = L * 3 / 4) {
-      long long tiles = 0, planes = 0;
-      for (int g = 0; g < n; ++g) {
-        const sbp_ctx* h = hs[g];
-        const int Lg = std::min(L, h->g.ns);
-        const int nz = (h->g.ns + Lg - 1) / Lg;
-        tiles += (long long)h->nxt * h->nyt * nz;
-        planes = std::max<long long>(planes, (h->g.ns + nz - 1) / nz + h->cl.r + h->cl.q + 1);
-      }
-      const long long cost = (tiles + cus - 1) / cus * planes;
-      if (best < 0 || cost < best) {
-        best = cost;
-        bestL = L;
-      }
-    }
-    for (int g = 0; g < n; ++g) {
-      hs[g]->zchunk = std::min(bestL, hs[g]->g.ns);
-      hs[g]->bounds_dirty = true;
-      int rc = prepare_bounds(hs[g]);
-      if (rc) return rc;
-    }
-  }
-  // the handles' own launch settings are restored when the call returns
-  struct Restore {
-    sbp_ctx** hs;
-    const std::vector<int>& z;
-    ~Restore() {
-      for (std::size_t g = 0; g < z.size(); ++g) {
-        hs[g]->zchunk = z[g];
-        hs[g]->bounds_dirty = true;
-      }
-    }
-  } restore{hs, zsave};
-  // groups: handles sorted by (order, tile height)
-  std::vector<int> ord(n);
-  for (int g = 0; g < n; ++g) ord[g] = g;
-  auto key = [&](int g) { return hs[g]->order * 100 + hs[g]->ty; };
-  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return key(a) < key(b); });
-  std::vector<int> gstart{0};
-  for (int p = 1; p < n; ++p)
-    if (key(ord[p]) != key(ord[p - 1])) gstart.push_back(p);
-  const int ngroups = (int)gstart.size();
-  gstart.push_back(n);
-  if (ngroups > kMaxGroups) return fail(SBP_EINVAL, "too many (order, tile height) groups in a batch");
-  // stage argument tables (5 stages x 2 ping-pong parities) and block prefixes
-  std::vector<StageArgs<T>> sa((std::size_t)10 * kMaxBatch);
-  std::vector<int> firsts((std::size_t)2 * kMaxGroups * (kMaxBatch + 1), 0);
-  std::vector<int> sblocks(ngroups), eblocks(ngroups);
-  bool buf_ok = true;
-  for (int G = 0; G < ngroups; ++G) {
-    int* fs = firsts.data() + (std::size_t)(2 * G) * (kMaxBatch + 1);
-    int* fe = firsts.data() + (std::size_t)(2 * G + 1) * (kMaxBatch + 1);
-    int ts = 0, te = 0;
-    for (int p = gstart[G]; p < gstart[G + 1]; ++p) {
-      sbp_ctx* h = hs[ord[p]];
-      StageArgs<T> a = stage_args<T>(h);
-      for (int k = 0; k < 5; ++k)
-        for (int P = 0; P < 2; ++P)
-          sa[(std::size_t)(k * 2 + P) * kMaxBatch + p] = stage_entry<T>(h, a, k, h->cur ^ P, dt[ord[p]], false);
-      const int q = p - gstart[G];
-      fs[q] = ts;
-      fe[q] = te;
-      ts += a.ntiles;
-      te += edge_blocks(a);
-      buf_ok = buf_ok && !a.plain && 12.0 * (double)a.field * sizeof(T) < 4294967296.0;
-    }
-    fs[gstart[G + 1] - gstart[G]] = ts;
-    fe[gstart[G + 1] - gstart[G]] = te;
-    sblocks[G] = ts;
-    eblocks[G] = te;
-  }
-  HIPCHK(hipStreamSynchronize(st));
-  HIPCHK(hipMemcpyAsync(base + R.stage, sa.data(), sa.size() * sizeof(StageArgs<T>), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(base + R.first, firsts.data(), firsts.size() * sizeof(int), hipMemcpyHostToDevice, st));
-  // handles with sources / receivers (compacted, in batch order)
-  std::vector<int> withsrc, withrec;
-  for (int g = 0; g < n; ++g) {
-    if (!hs[g]->src.empty()) withsrc.push_back(g);
-    if (hs[g]->nrec > 0) withrec.push_back(g);
-  }
-  std::vector<int> sfirst(withsrc.size() + 1, 0), rfirst(withrec.size() + 1, 0);
-  for (std::size_t q = 0; q < withsrc.size(); ++q) sfirst[q + 1] = sfirst[q] + (int)hs[withsrc[q]]->src.size();
-  for (std::size_t q = 0; q < withrec.size(); ++q) rfirst[q + 1] = rfirst[q] + hs[withrec[q]]->nrec;
-  HIPCHK(hipMemcpyAsync(base + R.src_first, sfirst.data(), sfirst.size() * sizeof(int), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemcpyAsync(base + R.rec_first, rfirst.data(), rfirst.size() * sizeof(int), hipMemcpyHostToDevice, st));
-  const StageArgs<T>* dsa = (const StageArgs<T>*)(base + R.stage);
-  const int* dfirst = (const int*)(base + R.first);
-
+  StepClock* clk = (StepClock*)(base + R.clock);
   std::vector<double> t0(n);
   for (int g = 0; g < n; ++g) t0[g] = hs[g]->t;
-  std::vector<SourceArgs<T>> stab;
-  std::vector<RecordArgs<T>> rtab;
-  for (int n0 = 0; n0 < nsteps; n0 += kBatchSteps) {
-    const int nc = std::min(kBatchSteps, nsteps - n0);
-    // the previous chunk's kernels and table copies are done before its host
-    // and device tables are overwritten
-    HIPCHK(hipStreamSynchronize(st));
-    // per-step source and receiver tables of this chunk
-    stab.assign((std::size_t)nc * 5 * std::max<std::size_t>(1, withsrc.size()), SourceArgs<T>{});
-    rtab.assign((std::size_t)nc * std::max<std::size_t>(1, withrec.size()), RecordArgs<T>{});
-    for (std::size_t q = 0; q < withsrc.size(); ++q) {
-      sbp_ctx* h = hs[withsrc[q]];
-      const double d = dt[withsrc[q]];
-      for (int nn = 0; nn < nc; ++nn) {
-        const int step = n0 + nn;
-        const double tn = t0[withsrc[q]] + step * d;
-        for (int k = 0; k < 5; ++k) {
-          const int c = h->cur ^ ((step * 5 + k) & 1);
-          T* qout = (T*)(h->ws + (c ? h->off_qa : h->off_qb));
-          stab[((std::size_t)nn * 5 + k) * withsrc.size() + q] = source_args<T>(h, k, d, tn + kRkC[k] * d, false, qout);
-        }
-      }
+  // step graphs (even, odd), captured for this call
+  hipGraphExec_t gx[2] = {nullptr, nullptr};
+  struct Drop {
+    hipGraphExec_t* g;
+    ~Drop() {
+      for (int i = 0; i < 2; ++i)
+        if (g[i]) (void)hipGraphExecDestroy(g[i]);
     }
-    for (std::size_t q = 0; q < withrec.size(); ++q) {
-      sbp_ctx* h = hs[withrec[q]];
-      for (int nn = 0; nn < nc; ++nn) {
-        const int step = n0 + nn;
-        const int c = h->cur ^ (((step + 1) * 5) & 1);  // state after the step
-        RecordArgs<T> r{};
-        r.q = (const T*)(h->ws + (c ? h->off_qb : h->off_qa));
-        r.field = h->field;
-        r.off = (const long long*)(h->ws + h->off_rec);
-        r.out = (T*)h->rec_out + (std::size_t)(h->rec_step + step) * h->nrec * 3;
-        rtab[(std::size_t)nn * withrec.size() + q] = r;
+  } drop{gx};
+  // FP32 batches replay captured step graphs; FP64 batches issue the same
+  // launches directly (their kernel bodies keep part of their state in
+  // scratch memory; see DESIGN: a graph-replayed FP64 batch went wrong)
+  const bool use_graph = h0->graphs && sizeof(T) == 4;
+  if (use_graph) {
+    if (!h0->cap) HIPCHK(hipStreamCreateWithFlags(&h0->cap, hipStreamNonBlocking));
+    for (int par = 0; par < 2 && par < nsteps; ++par) {
+      HIPCHK(hipStreamBeginCapture(h0->cap, hipStreamCaptureModeThreadLocal));
+      rc = batch_step_launches<T>(hs, P, par, h0->cap);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(h0->cap, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
       }
+      if (e != hipSuccess) return fail(SBP_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+      const hipError_t e2 = hipGraphInstantiate(&gx[par], g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (e2 != hipSuccess) return fail(SBP_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
     }
-    if (!withsrc.empty())
-      HIPCHK(hipMemcpyAsync(base + R.src, stab.data(), stab.size() * sizeof(SourceArgs<T>), hipMemcpyHostToDevice,
-                            st));
-    if (!withrec.empty())
-      HIPCHK(hipMemcpyAsync(base + R.rec, rtab.data(), rtab.size() * sizeof(RecordArgs<T>), hipMemcpyHostToDevice,
-                            st));
+  }
+  const std::size_t row = (std::size_t)n * kMaxSources;
+  for (int n0 = 0; n0 < nsteps; n0 += kBatchTabSteps) {
+    const int nc = std::min(kBatchTabSteps, nsteps - n0);
+    const int part = h0->btab_next;
+    h0->btab_next ^= 1;
+    char* dtab = base + R.gtab + (std::size_t)part * R.gtab_part;
+    if (P.nsrc > 0) {
+      if (h0->btab_used[part]) HIPCHK(hipEventSynchronize(h0->btab_ev[part]));
+      T* ht = (T*)(h0->btab_host + (std::size_t)part * R.gtab_part);
+      for (int nn = 0; nn < nc; ++nn)
+        for (int k = 0; k < 5; ++k)
+          for (int g : P.withsrc) {
+            const double tn = t0[g] + (n0 + nn) * dt[g];
+            for (std::size_t q = 0; q < hs[g]->src.size(); ++q)
+              ht[((std::size_t)nn * 5 + k) * row + (std::size_t)g * kMaxSources + q] =
+                  (T)(dt[g] * stf_value(hs[g]->src[q], tn + kRkC[k] * dt[g]));
+          }
+      HIPCHK(hipMemcpyAsync(dtab, ht, (std::size_t)nc * 5 * row * sizeof(T), hipMemcpyHostToDevice, st));
+      HIPCHK(hipEventRecord(h0->btab_ev[part], st));
+      h0->btab_used[part] = true;
+    }
+    HIPCHK(launch_clock_set(clk, dtab, n0, st));
     for (int nn = 0; nn < nc; ++nn) {
-      const int step = n0 + nn;
-      for (int k = 0; k < 5; ++k) {
-        const int P = (step * 5 + k) & 1;
-        for (int G = 0; G < ngroups; ++G) {
-          BatchArgs<T> b{};
-          b.args = dsa + (std::size_t)(k * 2 + P) * kMaxBatch + gstart[G];
-          b.n = gstart[G + 1] - gstart[G];
-          b.first = dfirst + (std::size_t)(2 * G) * (kMaxBatch + 1);
-          b.total = sblocks[G];
-          sbp_ctx* hg = hs[ord[gstart[G]]];
-          HIPCHK(launch_stage_batch<T>(hg->order, hg->ty, b, buf_ok, st));
-          b.first = dfirst + (std::size_t)(2 * G + 1) * (kMaxBatch + 1);
-          b.total = eblocks[G];
-          HIPCHK(launch_edge_batch<T>(hg->order, b, st));
-        }
-        if (!withsrc.empty()) {
-          SourceBatch<T> sb{};
-          sb.args = (const SourceArgs<T>*)(base + R.src) + ((std::size_t)nn * 5 + k) * withsrc.size();
-          sb.first = (const int*)(base + R.src_first);
-          sb.n = (int)withsrc.size();
-          sb.total = sfirst.back();
-          HIPCHK(launch_source_batch<T>(sb, st));
-        }
-      }
-      if (!withrec.empty()) {
-        RecordBatch<T> rb{};
-        rb.args = (const RecordArgs<T>*)(base + R.rec) + (std::size_t)nn * withrec.size();
-        rb.first = (const int*)(base + R.rec_first);
-        rb.n = (int)withrec.size();
-        rb.total = rfirst.back();
-        HIPCHK(launch_record_batch<T>(rb, st));
+      const int par = (n0 + nn) & 1;
+      if (use_graph) {
+        HIPCHK(hipGraphLaunch(gx[par], st));
+      } else if ((rc = batch_step_launches<T>(hs, P, par, st))) {
+        return rc;
       }
     }
   }
   // host-side state of every handle, as after nsteps calls of do_steps
   for (int g = 0; g < n; ++g) {
     sbp_ctx* h = hs[g];
-    h->cur ^= (5 * nsteps) & 1;
+    h->cur ^= nsteps & 1;
     h->steps += nsteps;
     if (h->nrec > 0) h->rec_step += nsteps;
     h->t = t0[g] + nsteps * dt[g];
   }
-  // the tables are read by kernels still in flight: keep them until done
+  // the graphs are destroyed on return: the work must be done
   HIPCHK(hipStreamSynchronize(st));
+  return SBP_OK;
+}
+
+// Batch launch-shape autotuner: times `reps` right-hand-side evaluations of
+// every grid (one batched stage launch each; they write only the
+// Runge-Kutta registers and the second state buffers) for the cost model's
+// chunk length and a few others, and keeps the fastest in every handle.
+template <typename T>
+int do_autotune_batch(sbp_ctx** hs, int n, int reps, int* bestL, double* best_ms) {
+  sbp_ctx* h0 = hs[0];
+  hipStream_t st = h0->stream;
+  const BatchRegion R = batch_region();
+  char* base = h0->ws + h0->off_batch;
+  int nsmax = 0;
+  for (int g = 0; g < n; ++g) nsmax = std::max(nsmax, hs[g]->g.ns);
+  std::vector<int> cands;
+  {
+    BatchSettings keep(hs, n);
+    int rc = batch_apply_L(hs, n, 0);
+    if (rc) return rc;
+    const int L0 = batch_cost_model_L(hs, n);
+    for (int L : {L0, L0 * 3 / 4, L0 * 3 / 2, L0 * 2, nsmax})
+      if (L >= 8 && std::find(cands.begin(), cands.end(), std::min(L, nsmax)) == cands.end())
+        cands.push_back(std::min(L, nsmax));
+  }
+  std::vector<double> dts(n, 1.0);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  double best = -1;
+  int bL = 0, rc = SBP_OK;
+  for (int L : cands) {
+    BatchSettings keep(hs, n);
+    if ((rc = batch_apply_L(hs, n, L))) break;
+    BatchPlan<T> P;
+    if ((rc = batch_upload<T>(hs, n, dts.data(), true, P))) break;
+    auto launch = [&]() -> int { return batch_stage_launch<T>(hs, P, 0, 0, st); };
+    if ((rc = launch())) break;  // warm-up
+    if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(SBP_EHIP, "hipEventRecord failed"); break; }
+    for (int r = 0; r < reps && rc == SBP_OK; ++r) rc = launch();
+    if (rc) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = fail(SBP_EHIP, "event timing failed");
+      break;
+    }
+    if (best < 0 || ms / reps < best) {
+      best = ms / reps;
+      bL = L;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  for (int g = 0; g < n; ++g) hs[g]->batch_L = bL;
+  if (bestL) *bestL = bL;
+  if (best_ms) *best_ms = best;
   return SBP_OK;
 }
 
@@ -1564,6 +1872,31 @@ int sbp_step(sbp_handle h, int nsteps, double dt) {
   return h->dtype == SBP_F32 ? do_steps<float>(h, nsteps, dt) : do_steps<double>(h, nsteps, dt);
 }
 
+// validation shared by the batch entry points (dt may be NULL)
+static int check_batch(sbp_handle* hs, int n, const double* dt) {
+  if (!hs) return fail(SBP_EINVAL, "NULL argument");
+  if (n < 1 || n > kMaxBatch) return fail(SBP_EINVAL, "n must be in [1, %d]", kMaxBatch);
+  for (int g = 0; g < n; ++g) {
+    sbp_ctx* h = hs[g];
+    if (!h) return fail(SBP_EINVAL, "NULL handle in batch (%d)", g);
+    for (int e = 0; e < g; ++e)
+      if (hs[e] == h) return fail(SBP_EINVAL, "handle %d appears twice in the batch", g);
+    if (h->dtype != hs[0]->dtype) return fail(SBP_EINVAL, "all handles of a batch need the same dtype");
+    if (h->stream != hs[0]->stream) return fail(SBP_EINVAL, "all handles of a batch need the same stream");
+    if (!h->have_material) return fail(SBP_ESTATE, "sbp_set_material has not been called (handle %d)", g);
+    if (dt && (!(dt[g] > 0) || !std::isfinite(dt[g]))) return fail(SBP_EINVAL, "need dt > 0 (handle %d)", g);
+  }
+  return SBP_OK;
+}
+
+int sbp_autotune_batch(sbp_handle* hs, int n, int reps, int* zchunk, double* ms) {
+  int rc = check_batch(hs, n, nullptr);
+  if (rc) return rc;
+  if (reps < 1) return fail(SBP_EINVAL, "reps must be >= 1");
+  return hs[0]->dtype == SBP_F32 ? do_autotune_batch<float>(hs, n, reps, zchunk, ms)
+                                 : do_autotune_batch<double>(hs, n, reps, zchunk, ms);
+}
+
 int sbp_step_batch(sbp_handle* hs, int n, int nsteps, const double* dt) {
   if (!hs || !dt) return fail(SBP_EINVAL, "NULL argument");
   if (n < 1 || n > kMaxBatch) return fail(SBP_EINVAL, "n must be in [1, %d]", kMaxBatch);
@@ -1703,7 +2036,7 @@ int sbp_fill_scratch(sbp_handle h, double value) {
 
 int sbp_checkpoint_id(sbp_handle h, long long* id) {
   if (!h || !id) return fail(SBP_EINVAL, "NULL argument");
-  *id = h->ck_valid ? h->ck_id : 0;
+  *id = (h->ck_valid && h->ck_steps == h->steps) ? h->ck_id : 0;
   return SBP_OK;
 }
 

@@ -175,45 +175,69 @@ __device__ __forceinline__ void node_rates(const T u[3][3], const T dv[3], const
 #ifndef SBP_STAGE_MIN_WAVES
 #define SBP_STAGE_MIN_WAVES 1  // minimum waves per SIMD the register allocation must allow
 #endif
-template <typename T, int ORDER, int TY, bool BUF>
-__device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile) {
+constexpr std::size_t kLdsBytes = 160 * 1024;
+
+// LDS of stage_body<T, ORDER, TY> (element offsets of its arrays in one
+// buffer): v window (64+2H) x (TY+2H), F_q window (64+2H) x TY, F_r window
+// 64 x (TY+2H), the per-thread ring of QD planes of F_s; sigma (6) and M_s
+// (3) of planes a .. a+R, read once from memory as the s-flux lead and kept
+// until the plane is the output plane (when the budget allows it; otherwise
+// plane a reloads them); the closure rows (D+, D- and their mirror images);
+// the penalty coefficients of the tile's q faces (TY rows) and r faces (64
+// columns) for the current plane, loaded one plane ahead like the field data
+// (a wait for a load issued later than the prefetch would also wait for the
+// prefetch), when the budget allows it
+template <typename T, int ORDER, int TY>
+struct StageLds {
   using S = Stencil<ORDER>;
+  static constexpr int R = S::R, Q = S::Q, H = Q, NT = 64 * TY;
+  static constexpr int VX = 64 + 2 * H, VY = TY + 2 * H, QX = 64 + 2 * H, RX = 64;
+  static constexpr int QD = R + Q + 1, SD = R + 1;
+  static constexpr int TABN = kMaxM * kMaxCols;
+  static constexpr int NFQ = kNumFaceCoef * TY, NFR = kNumFaceCoef * 64, NFE = 2 * NFQ + 2 * NFR;
+  static constexpr std::size_t n_lv = 3 * VX * VY, n_lq = 3 * QX * TY, n_lr = 3 * RX * VY, n_ring = QD * 3 * NT;
+  static constexpr std::size_t base_bytes = sizeof(T) * (n_lv + n_lq + n_lr + n_ring);
+  static constexpr bool SR = base_bytes + sizeof(T) * SD * 9 * NT <= kLdsBytes;
+  static constexpr std::size_t n_sring = SR ? SD * 9 * NT : 1;
+  static constexpr bool FL = base_bytes + (SR ? sizeof(T) * SD * 9 * NT : 0) +
+                                 sizeof(T) * (kClosureTab * TABN + NFE) <= kLdsBytes;
+  static constexpr std::size_t n_tab = kClosureTab * TABN, n_face = FL ? NFE : 1;
+  static constexpr std::size_t o_lv = 0, o_lq = o_lv + n_lv, o_lr = o_lq + n_lq, o_ring = o_lr + n_lr,
+                               o_sring = o_ring + n_ring, o_tab = o_sring + n_sring, o_face = o_tab + n_tab,
+                               total = o_face + n_face;
+  static constexpr std::size_t bytes = total * sizeof(T);
+};
+
+template <typename T, int ORDER, int TY, bool BUF>
+__device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile, char* lds) {
+  using S = Stencil<ORDER>;
+  using L = StageLds<T, ORDER, TY>;
   constexpr int R = S::R, Q = S::Q, M = S::M;
   constexpr int H = Q;            // halo width (Q >= R)
   constexpr int NT = 64 * TY;     // threads
-  constexpr int VX = 64 + 2 * H, VY = TY + 2 * H;  // v window
-  constexpr int QX = 64 + 2 * H;                   // F_q window (TY rows)
-  constexpr int RX = 64;                           // F_r window (VY rows)
-  constexpr int QD = R + Q + 1;   // s queue depth
+  constexpr int VX = L::VX, VY = L::VY;  // v window
+  constexpr int QX = L::QX;              // F_q window (TY rows)
+  constexpr int RX = L::RX;              // F_r window (VY rows)
+  constexpr int QD = L::QD;       // s queue depth
   constexpr int NYH = 2 * H * 64; // y-halo points
   constexpr int NXH = 2 * H * TY; // x-halo points
-  constexpr int TABN = kMaxM * kMaxCols;
+  constexpr int TABN = L::TABN;
   static_assert(NYH <= NT, "one y-halo point per thread");
   static_assert(TY >= M, "r closure rows must fit in one tile");
-  __shared__ T lv[3 * VX * VY];
-  __shared__ T lq[3 * QX * TY];
-  __shared__ T lr[3 * RX * VY];
-  __shared__ T ring[QD * 3 * NT];
-  // sigma (6) and M_s (3) of planes a .. a+R, read once from memory as the
-  // s-flux lead and kept until the plane is the output plane (when the LDS
-  // budget allows it; otherwise plane a reloads them)
-  constexpr int SD = R + 1;
-  constexpr std::size_t kBaseLds =
-      sizeof(T) * (3 * VX * VY + 3 * QX * TY + 3 * RX * VY + QD * 3 * NT);
-  constexpr bool SR = kBaseLds + sizeof(T) * SD * 9 * NT <= 160 * 1024;
-  __shared__ T sring[SR ? SD * 9 * NT : 1];
-  // closure coefficients (rows of D+, D-, and their mirror images)
-  __shared__ T ltab[kClosureTab * TABN];
-  // penalty coefficients of the tile's q faces (TY rows) and r faces (64
-  // columns) for the current plane, loaded one plane ahead like the field
-  // data (a wait for a load issued later than the prefetch would also wait
-  // for the prefetch); kept in LDS when the budget allows it
-  constexpr int NFQ = kNumFaceCoef * TY, NFR = kNumFaceCoef * 64;
-  constexpr int NFE = 2 * NFQ + 2 * NFR;
-  constexpr bool FL = kBaseLds + (SR ? sizeof(T) * SD * 9 * NT : 0) +
-                          sizeof(T) * (kClosureTab * TABN + NFE) <= 160 * 1024;
+  static_assert(L::bytes <= kLdsBytes, "stage tile exceeds the LDS");
+  T* const lv = reinterpret_cast<T*>(lds) + L::o_lv;
+  T* const lq = reinterpret_cast<T*>(lds) + L::o_lq;
+  T* const lr = reinterpret_cast<T*>(lds) + L::o_lr;
+  T* const ring = reinterpret_cast<T*>(lds) + L::o_ring;
+  constexpr int SD = L::SD;
+  constexpr bool SR = L::SR;
+  T* const sring = reinterpret_cast<T*>(lds) + L::o_sring;
+  T* const ltab = reinterpret_cast<T*>(lds) + L::o_tab;
+  constexpr int NFQ = L::NFQ, NFR = L::NFR;
+  constexpr int NFE = L::NFE;
+  constexpr bool FL = L::FL;
   constexpr int KF = FL ? (NFE + NT - 1) / NT : 1;
-  __shared__ T lface[FL ? NFE : 1];
+  T* const lface = reinterpret_cast<T*>(lds) + L::o_face;
 
   if (tile >= A.ntiles) return;
   const int xt = tile % A.nxt;
@@ -752,9 +776,23 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
 // from memory.  Same arithmetic as the stage kernel: interior rows from the
 // interior stencil, boundary rows from the closure table, fluxes by flux3,
 // rates by node_rates, penalties by face_penalty, then the Runge-Kutta update.
+// LDS of edge_body<T, ORDER, KZ>: the closure rows, the patch (v, the
+// tangential flux and the s flux of 64 + 2H strip points x KZ + 2H planes)
+// and, for the column strip, the partial sums of its q closure row over
+// columns nq-2 .. nq-NC (D+ part 3, D- part 3) per node of the block
 template <typename T, int ORDER, int KZ>
-__device__ __forceinline__ void edge_body(const StageArgs<T>& A, int b) {
+struct EdgeLds {
+  static constexpr int H = Stencil<ORDER>::Q, NT = 64 * KZ;
+  static constexpr int PT = 64 + 2 * H, PK = KZ + 2 * H, NP = PT * PK;
+  static constexpr std::size_t o_tab = 0, o_lp = o_tab + kClosureTab * kMaxM * kMaxCols, o_lqc = o_lp + 9 * NP,
+                               total = o_lqc + 6 * NT;
+  static constexpr std::size_t bytes = total * sizeof(T);
+};
+
+template <typename T, int ORDER, int KZ>
+__device__ __forceinline__ void edge_body(const StageArgs<T>& A, int b, char* lds) {
   using S = Stencil<ORDER>;
+  using L = EdgeLds<T, ORDER, KZ>;
   constexpr int R = S::R, Q = S::Q, M = S::M;
   constexpr int QD = R + Q + 1;
   constexpr int NC = M + Q;  // columns of a closure row
@@ -762,12 +800,11 @@ __device__ __forceinline__ void edge_body(const StageArgs<T>& A, int b) {
   constexpr int TABN = kMaxM * kMaxCols;
   constexpr int H = Q;
   constexpr int NT = 64 * KZ;
-  constexpr int PT = 64 + 2 * H, PK = KZ + 2 * H, NP = PT * PK;
-  __shared__ T ltab[kClosureTab * TABN];
-  __shared__ T lp[9 * NP];  // v (3), tangential flux (3), s flux (3)
-  // column strip: sums over columns nq-2 .. nq-NC of its q closure row
-  // (D+ part 3, D- part 3) per node of the block
-  __shared__ T lqc[6 * NT];
+  constexpr int PT = L::PT, NP = L::NP;
+  static_assert(L::bytes <= kLdsBytes, "edge patch exceeds the LDS");
+  T* const ltab = reinterpret_cast<T*>(lds) + L::o_tab;
+  T* const lp = reinterpret_cast<T*>(lds) + L::o_lp;    // v (3), tangential flux (3), s flux (3)
+  T* const lqc = reinterpret_cast<T*>(lds) + L::o_lqc;
 
   const int nq = A.nq, nr = A.nr, ns = A.ns;
   const int ex = A.ex, ey = A.ey;
@@ -1010,14 +1047,16 @@ __device__ __forceinline__ void edge_body(const StageArgs<T>& A, int b) {
 // per-grid block counts; the grid's arguments are read from a device table)
 template <typename T, int ORDER, int TY, bool BUF>
 __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(const StageArgs<T> A) {
+  __shared__ __align__(16) char lds[StageLds<T, ORDER, TY>::bytes];
   // XCD-aware tile order: consecutive tiles land on the same XCD
   const int per = gridDim.x >> 3;
-  stage_body<T, ORDER, TY, BUF>(A, (blockIdx.x & 7) * per + (blockIdx.x >> 3));
+  stage_body<T, ORDER, TY, BUF>(A, (blockIdx.x & 7) * per + (blockIdx.x >> 3), lds);
 }
 
 template <typename T, int ORDER, int KZ>
 __global__ __launch_bounds__(64 * KZ) void edge_kernel(const StageArgs<T> A) {
-  edge_body<T, ORDER, KZ>(A, blockIdx.x);
+  __shared__ __align__(16) char lds[EdgeLds<T, ORDER, KZ>::bytes];
+  edge_body<T, ORDER, KZ>(A, blockIdx.x, lds);
 }
 
 // last entry of first[0 .. n-1] (non-decreasing, first[0] = 0) that is <= item
@@ -1039,7 +1078,8 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel_bat
   const int g = batch_find(B.first, B.n, item);
   // a private copy: loaded once, and no store of the kernel can alias it
   const StageArgs<T> A = B.args[g];
-  stage_body<T, ORDER, TY, BUF>(A, item - B.first[g]);
+  __shared__ __align__(16) char lds[StageLds<T, ORDER, TY>::bytes];
+  stage_body<T, ORDER, TY, BUF>(A, item - B.first[g], lds);
 }
 
 template <typename T, int ORDER, int KZ>
@@ -1048,7 +1088,68 @@ __global__ __launch_bounds__(64 * KZ) void edge_kernel_batch(const BatchArgs<T> 
   if (item >= B.total) return;
   const int g = batch_find(B.first, B.n, item);
   const StageArgs<T> A = B.args[g];
-  edge_body<T, ORDER, KZ>(A, item - B.first[g]);
+  __shared__ __align__(16) char lds[EdgeLds<T, ORDER, KZ>::bytes];
+  edge_body<T, ORDER, KZ>(A, item - B.first[g], lds);
+}
+
+// ---------------------------------------------------------------------------
+// Batched stage: one launch per Runge-Kutta stage for the stage tiles and
+// edge blocks of every grid of a batch, whatever their interior order, with
+// the same kernel bodies as stage_kernel / edge_kernel.  The LDS buffer is
+// sized for the largest body of the orders the kernel serves.
+template <typename T>
+struct PersistOrders;
+template <>
+struct PersistOrders<float> {
+  static constexpr int lo = 2, hi = 7;
+};
+template <>
+struct PersistOrders<double> {
+  static constexpr int lo = 2, hi = 6;  // order 7's stage tile exceeds the LDS in double
+};
+
+// the orders a kernel serves: bit o of MASK
+template <typename T, unsigned MASK, int O>
+constexpr std::size_t persist_lds_upto() {
+  if constexpr (O < PersistOrders<T>::lo) {
+    return 0;
+  } else {
+    const std::size_t a = StageLds<T, O, 8>::bytes, b = EdgeLds<T, O, 8>::bytes;
+    const std::size_t m = ((MASK >> O) & 1u) ? (a > b ? a : b) : 0;
+    const std::size_t r = persist_lds_upto<T, MASK, O - 1>();
+    return m > r ? m : r;
+  }
+}
+
+template <typename T, unsigned MASK, int O>
+__device__ __forceinline__ void persist_dispatch(const StageArgs<T>& A, const BatchItem& w, char* lds) {
+  if constexpr (O >= PersistOrders<T>::lo) {
+    if constexpr ((MASK >> O) & 1u) {
+      if (w.order == O) {
+        if (w.kind == 0)
+          stage_body<T, O, 8, true>(A, w.local, lds);
+        else
+          edge_body<T, O, 8>(A, w.local, lds);
+        return;
+      }
+    }
+    persist_dispatch<T, MASK, O - 1>(A, w, lds);
+  }
+}
+
+// One launch over the whole work list: block b takes item (b & 7) of the
+// interleaved list, so that the hardware, dispatching blocks in order and
+// round-robin over the 8 XCDs, hands each XCD its own segment, longest
+// items first; a slot past the end of its segment is an empty block.
+template <typename T, unsigned MASK>
+__global__ __launch_bounds__(512, SBP_STAGE_MIN_WAVES) void stage_kernel_worklist(const PersistArgs<T> P) {
+  __shared__ __align__(16) char lds[persist_lds_upto<T, MASK, PersistOrders<T>::hi>()];
+  const int sg = blockIdx.x & 7;
+  const int item = P.seg[sg] + (int)(blockIdx.x >> 3);
+  if (item >= P.seg[sg + 1]) return;
+  const BatchItem w = P.items[item];
+  const StageArgs<T> A = P.args[w.grid];
+  persist_dispatch<T, MASK, PersistOrders<T>::hi>(A, w, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1059,7 +1160,9 @@ template <typename T>
 __device__ __forceinline__ void source_body(const SourceArgs<T>& S, const int s) {
   const int w = S.width;
   const int n = w * w * w;
-  const T gdt = S.clock ? static_cast<const T*>(S.clock->gtab)[((std::size_t)S.clock->step * 5 + S.stage) * kMaxSources + s]
+  const int stride = S.tab_stride ? S.tab_stride : kMaxSources;
+  const T gdt = S.clock ? static_cast<const T*>(S.clock->gtab)[((std::size_t)S.clock->step * 5 + S.stage) * stride +
+                                                             S.tab_off + s]
                         : S.gdt[s];
   for (int t = threadIdx.x; t < n; t += blockDim.x) {
     const int a = t % w, b = (t / w) % w, c = t / (w * w);
@@ -1096,8 +1199,13 @@ __global__ void record_kernel_batch(const RecordBatch<T> B) {
   const RecordArgs<T>& R = B.args[g];
   const int r = item - B.first[g];
   const long long o = R.off[r];
+  std::size_t at = (std::size_t)r * 3;
+  if (B.clock) {
+    const int nrec = B.first[g + 1] - B.first[g];
+    at += (std::size_t)(R.base + B.clock->rec0 + B.clock->step) * nrec * 3;
+  }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) R.out[(std::size_t)r * 3 + c] = R.q[c * R.field + o];
+  for (int c = 0; c < 3; ++c) R.out[at + c] = R.q[c * R.field + o];
 }
 
 // receivers: out[(slot * nrec + r) * 3 + c] = v_c(node_r), slot = the clock's
@@ -1297,6 +1405,30 @@ hipError_t launch_record_batch(const RecordBatch<T>& b, hipStream_t st) {
   return hipGetLastError();
 }
 
+// one kernel per set of orders that batches commonly mix (the register
+// allocation of a kernel is that of its most demanding body), and one for
+// every order
+template <typename T>
+hipError_t launch_stage_worklist(const PersistArgs<T>& p, unsigned orders, int blocks, hipStream_t st) {
+  constexpr unsigned kAll = ((1u << (PersistOrders<T>::hi + 1)) - 1) & ~3u;
+  if ((orders & ~(1u << 4)) == 0)
+    hipLaunchKernelGGL((stage_kernel_worklist<T, 1u << 4>), dim3(blocks), dim3(64, 8), 0, st, p);
+  else if ((orders & ~(1u << 6)) == 0)
+    hipLaunchKernelGGL((stage_kernel_worklist<T, 1u << 6>), dim3(blocks), dim3(64, 8), 0, st, p);
+  else if ((orders & ~((1u << 4) | (1u << 6))) == 0)
+    hipLaunchKernelGGL((stage_kernel_worklist<T, (1u << 4) | (1u << 6)>), dim3(blocks), dim3(64, 8), 0, st, p);
+  else if ((orders & ~kAll) == 0)
+    hipLaunchKernelGGL((stage_kernel_worklist<T, kAll>), dim3(blocks), dim3(64, 8), 0, st, p);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename T>
+bool worklist_order_ok(int order) {
+  return order >= PersistOrders<T>::lo && order <= PersistOrders<T>::hi;
+}
+
 template <typename T>
 hipError_t launch_source(const SourceArgs<T>& s, int nsrc, hipStream_t st) {
   hipLaunchKernelGGL(source_kernel<T>, dim3(nsrc), dim3(256), 0, st, s);
@@ -1340,6 +1472,10 @@ template hipError_t launch_source_batch<float>(const SourceBatch<float>&, hipStr
 template hipError_t launch_source_batch<double>(const SourceBatch<double>&, hipStream_t);
 template hipError_t launch_record_batch<float>(const RecordBatch<float>&, hipStream_t);
 template hipError_t launch_record_batch<double>(const RecordBatch<double>&, hipStream_t);
+template hipError_t launch_stage_worklist<float>(const PersistArgs<float>&, unsigned, int, hipStream_t);
+template hipError_t launch_stage_worklist<double>(const PersistArgs<double>&, unsigned, int, hipStream_t);
+template bool worklist_order_ok<float>(int);
+template bool worklist_order_ok<double>(int);
 template hipError_t launch_source<float>(const SourceArgs<float>&, int, hipStream_t);
 template hipError_t launch_source<double>(const SourceArgs<double>&, int, hipStream_t);
 template hipError_t launch_record<float>(const float*, std::size_t, const long long*, int, float*,

@@ -54,6 +54,11 @@ struct StepClock {
   int pad;
 };
 
+// batched stepping: receiver slot of a step = base (the handle's recorded
+// steps before the call) + the clock's rec0 (steps before the chunk) + step
+template <typename T>
+struct RecordArgs;
+
 template <typename T>
 struct SourceArgs {
   T* dq;
@@ -67,6 +72,8 @@ struct SourceArgs {
   T Bk;
   const StepClock* clock;  // non-null: dt * g from the clock's table
   int stage;               // Runge-Kutta stage (index into the clock's table)
+  int tab_stride;          // table entries per (step, stage) (0 means kMaxSources)
+  int tab_off;             // this grid's first entry in a (step, stage) row
 };
 
 template <typename T>
@@ -79,6 +86,24 @@ struct EnergyArgs {
   int px, nq, nr, ns, m;
   double h[3];
   double w[kMaxM];
+};
+
+// Work list of the batched stage kernel: one entry per block of work (a
+// stage-kernel tile or an edge-kernel strip block of one grid), split into 8
+// segments (one per XCD: block b of the launch takes entry b / 8 of segment
+// b % 8); within a segment, longest first.
+struct BatchItem {
+  int grid;   // index into the argument table
+  int kind;   // 0 stage tile, 1 edge block
+  int local;  // tile / block index within the grid
+  int order;  // interior order of the grid
+};
+
+template <typename T>
+struct PersistArgs {
+  const StageArgs<T>* args;  // per grid, this stage and ping-pong parity
+  const BatchItem* items;
+  const int* seg;            // segment starts, 9 entries (seg[8] = number of items)
 };
 
 // several grids in one launch: args[g] for grid g, whose blocks are
@@ -95,7 +120,8 @@ struct RecordArgs {
   const T* q;
   std::size_t field;
   const long long* off;
-  T* out;  // this step's slot
+  T* out;          // this step's slot, or the first slot with a clock
+  long long base;  // with a clock: slot of the call's first step
 };
 
 template <typename T>
@@ -110,6 +136,7 @@ struct RecordBatch {
   const RecordArgs<T>* args;
   const int* first;
   int n, total;
+  const StepClock* clock;  // non-null: slot from the clock
 };
 
 template <typename T>
@@ -124,6 +151,13 @@ template <typename T>
 hipError_t launch_edge_batch(int order, const BatchArgs<T>& b, hipStream_t st);
 template <typename T>
 hipError_t launch_source_batch(const SourceBatch<T>& b, hipStream_t st);
+// batched stage over a work list: `blocks` (8 x the longest segment) blocks
+// of 64 x 8 threads (every stage tile has 8 rows); `orders` has bit o set
+// for every interior order o in the list
+template <typename T>
+hipError_t launch_stage_worklist(const PersistArgs<T>& p, unsigned orders, int blocks, hipStream_t st);
+template <typename T>
+bool worklist_order_ok(int order);
 template <typename T>
 hipError_t launch_record_batch(const RecordBatch<T>& b, hipStream_t st);
 template <typename T>

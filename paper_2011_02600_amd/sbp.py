@@ -62,6 +62,7 @@ def lib():
             "sbp_set_addressing": [c_void_p, c_int],
             "sbp_step_batch": [c_void_p, c_int, c_int, P(c_double)],
             "sbp_autotune": [c_void_p, c_int, P(c_int), P(c_int), P(c_double)],
+            "sbp_autotune_batch": [c_void_p, c_int, c_int, P(c_int), P(c_double)],
             "sbp_profile": [c_void_p, P(c_double), P(c_double), P(ctypes.c_longlong), P(ctypes.c_longlong)],
             "sbp_destroy": [c_void_p],
             "sbp_adjoint_bytes": [c_void_p, c_int, c_int, P(c_size_t)],
@@ -205,6 +206,17 @@ def sbp_autotune(h, reps=5):
     ty, zc, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
     _check(lib().sbp_autotune(h, int(reps), ctypes.byref(ty), ctypes.byref(zc), ctypes.byref(ms)))
     return ty.value, zc.value, ms.value
+
+
+def sbp_autotune_batch(handles, reps=3):
+    """Time batched right-hand-side launches for a few s-chunk lengths and
+    keep the fastest for later sbp_step_batch calls of these handles;
+    returns (chunk length, ms per batched stage launch)."""
+    n = len(handles)
+    arr = (ctypes.c_void_p * n)(*handles)
+    L, ms = ctypes.c_int(), ctypes.c_double()
+    _check(lib().sbp_autotune_batch(arr, n, int(reps), ctypes.byref(L), ctypes.byref(ms)))
+    return L.value, ms.value
 
 
 def sbp_set_addressing(h, plain):
