@@ -75,6 +75,22 @@ int sbp_nn_sum_rows(int S, long long n, const float* x, float* out, int accumula
 int sbp_nn_mse(long long n, const float* y, const float* t, float* dy, float scale, double* part, double* loss,
                void* stream);
 
+/*
+ * sbp_nn_mse without the workspace argument, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid allocation): dy = scale (y - t) (dy may be NULL) and
+ * *loss = 1/2 sum (y - t)^2, summed in double (per chunk of 1024 elements,
+ * then over the chunks, both in a fixed order; equal to sbp_nn_mse up to
+ * the order of the double sums).  Allocates nothing: its scratch is a
+ * static device array of 65536 + 1 doubles (512 KiB per GPU, held until the
+ * process ends), so n is at most 65536 * 1024 = 67108864 elements; larger n
+ * is SBP_NN_EINVAL with a message naming the limit.  Calls on one GPU share
+ * that array: calls that overlap in time on one GPU (other streams, other
+ * threads) race and must not be issued.  Synchronises the stream.
+ */
+int sbp_nn_mse_noalloc(long long n, const float* y, const float* t, float* dy, float scale, double* loss,
+                       void* stream);
+
 /* One Adam step (Kingma & Ba) on n parameters, step >= 1 (bias correction). */
 int sbp_nn_adam(long long n, float* p, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
                 int step, void* stream);

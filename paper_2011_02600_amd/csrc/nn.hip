@@ -8,6 +8,8 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <mutex>
 
 #include "../../include/sbp_nn.h"
 
@@ -249,6 +251,78 @@ __global__ void axpy_kernel(long long n, float a, const float* x, float* y) {
 
 int blocks_for(long long n) { return (int)std::min<long long>((n + 255) / 256, 1 << 16); }
 
+// ---- allocation-free misfit (sbp_nn_mse_noalloc) ------------------------------
+// Its scratch lives in a file-scope device array (one copy per GPU, held
+// until the process ends): kMseMaxParts partial sums, one per chunk of
+// kMseChunk elements, then the total.  Host code never passes the array's
+// name to a kernel (on the host it is only a stand-in for the symbol): it
+// uses the device address hipGetSymbolAddress returns for the current GPU.
+constexpr int kMseChunk = 1024;
+constexpr int kMseMaxParts = 65536;
+static __device__ __align__(256) double scratch[kMseMaxParts + 1];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// device address of `scratch` on the current GPU (looked up once per GPU);
+// null (error text set) on failure
+double* scratch_on_current_device(char* err, std::size_t nerr) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    snprintf(err, nerr, "no usable current device (%s)", hipGetErrorString(e));
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      snprintf(err, nerr, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+      return nullptr;
+    }
+    g_scratch_dev[dev] = static_cast<double*>(ptr);
+  }
+  return g_scratch_dev[dev];
+}
+
+// part[b] = sum over elements [b chunk, (b + 1) chunk) of (y - t)^2, dy =
+// scale (y - t); 256 threads per chunk, fixed-order tree reduction
+__global__ __launch_bounds__(256) void mse_chunk_kernel(long long n, const float* y, const float* t, float* dy,
+                                                        float scale, long long chunk, double* part) {
+  __shared__ double red[256];
+  const long long e0 = (long long)blockIdx.x * chunk;
+  const long long e1 = min(n, e0 + chunk);
+  double acc = 0.0;
+  for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const float d = y[e] - t[e];
+    if (dy) dy[e] = scale * d;
+    acc += (double)d * d;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// out[0] = sum of part[0 .. nparts-1] (one block, fixed order)
+__global__ __launch_bounds__(1024) void sum_parts_kernel(int nparts, const double* part, double* out) {
+  __shared__ double red[1024];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += blockDim.x) acc += part[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 512; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
 thread_local char g_nn_err[256] = "";
 
 int nn_fail(const char* msg) {
@@ -359,6 +433,32 @@ int sbp_nn_mse(long long n, const float* y, const float* t, float* dy, float sca
   double s = 0.0;
   for (int i = 0; i < SBP_NN_MSE_PARTS; ++i) s += h[i];
   *loss = 0.5 * s;
+  return nn_status();
+}
+
+int sbp_nn_mse_noalloc(long long n, const float* y, const float* t, float* dy, float scale, double* loss,
+                       void* stream) {
+  if (n <= 0 || !y || !t || !loss) return nn_fail("invalid mse arguments");
+  const long long nparts = (n + kMseChunk - 1) / kMseChunk;
+  if (nparts > kMseMaxParts) {
+    snprintf(g_nn_err, sizeof(g_nn_err),
+             "n = %lld exceeds the static scratch of sbp_nn_mse_noalloc: at most %lld elements (%d partial sums of "
+             "%d); use sbp_nn_mse with a workspace",
+             n, (long long)kMseMaxParts * kMseChunk, kMseMaxParts, kMseChunk);
+    return SBP_NN_EINVAL;
+  }
+  double* sc = scratch_on_current_device(g_nn_err, sizeof(g_nn_err));
+  if (!sc) return SBP_NN_EHIP;
+  hipStream_t st = (hipStream_t)stream;
+  // every partial is written before it is read: nothing to clear
+  hipLaunchKernelGGL(mse_chunk_kernel, dim3((unsigned)nparts), dim3(256), 0, st, n, y, t, dy, scale,
+                     (long long)kMseChunk, sc);
+  hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(1024), 0, st, (int)nparts, sc, sc + kMseMaxParts);
+  double h = 0.0;
+  hipError_t e = hipMemcpyAsync(&h, sc + kMseMaxParts, sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return nn_status();
+  *loss = 0.5 * h;
   return nn_status();
 }
 

@@ -49,6 +49,7 @@ def lib():
             "sbp_nn_add_rows": [c_int, c_ll, c_void_p, c_void_p, c_void_p],
             "sbp_nn_sum_rows": [c_int, c_ll, c_void_p, c_void_p, c_int, c_void_p],
             "sbp_nn_mse": [c_ll, c_void_p, c_void_p, c_void_p, c_float, c_void_p, P(ctypes.c_double), c_void_p],
+            "sbp_nn_mse_noalloc": [c_ll, c_void_p, c_void_p, c_void_p, c_float, P(ctypes.c_double), c_void_p],
             "sbp_nn_adam": [c_ll, c_void_p, c_void_p, c_void_p, c_void_p, c_float, c_float, c_float, c_float, c_int,
                             c_void_p],
             "sbp_nn_axpy": [c_ll, c_float, c_void_p, c_void_p, c_void_p],
