@@ -195,7 +195,7 @@ int check_dims(int nq, int nr, int ns, int order, int dtype) {
 // parities, the work list and its segments, the clock, the source-time table
 // (two parts).
 struct BatchRegion {
-  std::size_t stage, first, src, src_first, rec, rec_first, items, seg, clock, gtab, gtab_part, total;
+  std::size_t stage, first, src, src_first, rec, rec_first, pen_first, items, seg, clock, gtab, gtab_part, total;
 };
 BatchRegion batch_region() {
   BatchRegion r{};
@@ -211,6 +211,7 @@ BatchRegion batch_region() {
   r.src_first = take((std::size_t)(kMaxBatch + 1) * sizeof(int));
   r.rec = take((std::size_t)2 * kMaxBatch * sizeof(RecordArgs<double>));
   r.rec_first = take((std::size_t)(kMaxBatch + 1) * sizeof(int));
+  r.pen_first = take((std::size_t)(kMaxBatch + 1) * sizeof(int));
   r.items = take((std::size_t)kMaxItems * sizeof(BatchItem));
   r.seg = take(9 * sizeof(int));
   r.clock = take(sizeof(StepClock));
@@ -566,10 +567,11 @@ StageArgs<T> stage_entry(sbp_ctx* h, const StageArgs<T>& a, int k, int c, double
 }
 
 // One Runge-Kutta stage (or the right-hand side alone) on stream st: the
-// stage kernel, the edge kernel, the point sources (dt * g from the clock's
-// table when clock is not null, else evaluated here at tstage).  With
-// profiling on (only on the handle's own stream) the stage and edge kernels
-// are bracketed by events and the host waits for them.
+// stage kernel, the edge kernel, the boundary penalties, the point sources
+// (dt * g from the clock's table when clock is not null, else evaluated here
+// at tstage).  With profiling on (only on the handle's own stream) the stage
+// kernel, and the edge and penalty kernels together, are bracketed by events
+// and the host waits for them.
 template <typename T>
 int run_stage(sbp_ctx* h, StageArgs<T>& a, int k, double dt, double tstage, bool rhs_only, T* qin, T* qout,
               hipStream_t st, const StepClock* clock) {
@@ -580,6 +582,7 @@ int run_stage(sbp_ctx* h, StageArgs<T>& a, int k, double dt, double tstage, bool
   HIPCHK(launch_stage<T>(h->order, h->ty, a, st));
   if (prof) HIPCHK(hipEventRecord(h->ev[1], st));
   if (h->ex || h->ey) HIPCHK(launch_edge<T>(h->order, a, st));
+  if (a.sat) HIPCHK(launch_penalty<T>(a, st));
   if (prof) {
     HIPCHK(hipEventRecord(h->ev[2], st));
     HIPCHK(hipEventSynchronize(h->ev[2]));
@@ -838,6 +841,8 @@ struct BatchPlan {
   bool worklist = true;  // one launch over the work list (else one per order)
   unsigned orders = 0;   // bit o: interior order o present
   int maxseg = 0;        // longest work-list segment
+  int npen = 0;          // surface nodes of all grids (penalty launch)
+  int n = 0;             // grids
   int ngroups = 0;
   std::vector<int> gstart, ord, sblocks, eblocks;
   std::vector<int> withsrc, withrec;
@@ -857,6 +862,7 @@ int batch_upload(sbp_ctx** hs, int n, const double* dt, bool rhs_only, BatchPlan
     buf_ok = buf_ok && worklist_order_ok<T>(hs[g]->order);
   }
   P.worklist = buf_ok;
+  P.n = n;
   P.orders = 0;
   for (int g = 0; g < n; ++g) P.orders |= 1u << hs[g]->order;
   // stage argument tables: entry (k, P) of handle g, P the parity of the stage
@@ -919,10 +925,19 @@ int batch_upload(sbp_ctx** hs, int n, const double* dt, bool rhs_only, BatchPlan
     }
     HIPCHK(hipMemcpyAsync(base + R.first, firsts.data(), firsts.size() * sizeof(int), hipMemcpyHostToDevice, st));
   }
-  if (rhs_only) {
+  // boundary penalties: surface nodes of every grid, in the order of the
+  // stage argument table
+  {
+    std::vector<int> pfirst(n + 1, 0);
+    for (int q = 0; q < n; ++q) {
+      const sbp_ctx* h = hs[P.worklist ? q : P.ord[q]];
+      pfirst[q + 1] = pfirst[q] + (int)surface_nodes(h->g.nq, h->g.nr, h->g.ns);
+    }
+    P.npen = pfirst[n];
+    HIPCHK(hipMemcpyAsync(base + R.pen_first, pfirst.data(), pfirst.size() * sizeof(int), hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));  // the host tables are released on return
-    return SBP_OK;
   }
+  if (rhs_only) return SBP_OK;
   // sources: handles with sources, compacted; entry (k, P) of each; the
   // source-time factor from the clock's table, row (step, k) of n x
   // kMaxSources entries, this handle's at g * kMaxSources
@@ -976,6 +991,20 @@ int batch_upload(sbp_ctx** hs, int n, const double* dt, bool rhs_only, BatchPlan
   return SBP_OK;
 }
 
+// The boundary penalties of every grid of a batch (one launch), after the
+// stage launches.
+template <typename T>
+int batch_penalty_launch(sbp_ctx** hs, const BatchPlan<T>& P, const StageArgs<T>* dsa, hipStream_t st) {
+  const BatchRegion R = batch_region();
+  BatchArgs<T> b{};
+  b.args = dsa;
+  b.first = (const int*)(hs[0]->ws + hs[0]->off_batch + R.pen_first);
+  b.n = P.n;
+  b.total = P.npen;
+  HIPCHK(launch_penalty_batch<T>(b, st));
+  return SBP_OK;
+}
+
 // One batched stage launch (all grids) for argument entry e = k * 2 + P.
 template <typename T>
 int batch_stage_launch(sbp_ctx** hs, const BatchPlan<T>& P, int k, int e, hipStream_t st) {
@@ -989,7 +1018,7 @@ int batch_stage_launch(sbp_ctx** hs, const BatchPlan<T>& P, int k, int e, hipStr
     pa.items = (const BatchItem*)(base + R.items);
     pa.seg = (const int*)(base + R.seg);
     HIPCHK(launch_stage_worklist<T>(pa, P.orders, 8 * P.maxseg, st));
-    return SBP_OK;
+    return batch_penalty_launch<T>(hs, P, dsa, st);
   }
   const int* dfirst = (const int*)(base + R.first);
   for (int G = 0; G < P.ngroups; ++G) {
@@ -1004,7 +1033,7 @@ int batch_stage_launch(sbp_ctx** hs, const BatchPlan<T>& P, int k, int e, hipStr
     b.total = P.eblocks[G];
     HIPCHK(launch_edge_batch<T>(order, b, st));
   }
-  return SBP_OK;
+  return batch_penalty_launch<T>(hs, P, dsa, st);
 }
 
 // The launches of one batched step of parity par (0: even step of the call)
@@ -1375,6 +1404,7 @@ int stage_explicit(sbp_ctx* h, const StageArgs<T>& base, int k, double dt, doubl
   b.sat = sat ? 1 : 0;
   HIPCHK(launch_stage<T>(h->order, h->ty, b, h->stream));
   if (h->ex || h->ey) HIPCHK(launch_edge<T>(h->order, b, h->stream));
+  if (sat) HIPCHK(launch_penalty<T>(b, h->stream));
   if (sources && !h->src.empty()) {
     SourceArgs<T> s = source_args<T>(h, k, dt, tstage, rhs_only, qout);
     s.dq = dq;

@@ -4,9 +4,13 @@
 // Stage kernel (fused; one launch per stage):
 //   for every node: RHS = volume terms (D+ on the velocities in the
 //   non-conservative term, D- on the conservative stress flux, metric and
-//   material weights; eq. gen_hyp_transformed_discrete) + boundary penalties
-//   (eq. SAT_General / eq. SAT_free_surface), then
+//   material weights; eq. gen_hyp_transformed_discrete), then
 //   dQ <- A_k dQ + dt RHS,  Q_out <- Q_in + B_k dQ.
+// Penalty kernel (after the stage and edge kernels): at every node of the
+//   block's surface, the boundary penalties of its faces (eq. SAT_General /
+//   eq. SAT_free_surface) enter the same update, dQ += dt P, Q_out += B_k dt P
+//   (the update is linear in the right-hand side).  Keeping them out of the
+//   stage kernel's plane loop keeps that loop's registers for its own data.
 // Q_in and Q_out are different buffers (ping-pong), so neighbours are never
 // read after being overwritten.
 //
@@ -135,6 +139,15 @@ __device__ __forceinline__ void flux3(T m0, T m1, T m2, T sxx, T syy, T szz, T s
   f[2] = fma(m2, szz, fma(m1, syz, m0 * sxz));
 }
 
+// In double precision the scheduler's hoisting of every stencil load of a
+// derivative (three components, value and flux) ahead of its arithmetic
+// takes more registers than a thread has: a fence between components keeps
+// one component's loads in flight at a time.
+template <typename T>
+__device__ __forceinline__ void sched_fence() {
+  if constexpr (sizeof(T) == 8) __builtin_amdgcn_sched_barrier(0);
+}
+
 // ---------------------------------------------------------------------------
 // pointwise part of the right-hand side at one node: stress rates from the
 // velocity derivatives u[xi][i] = D+_xi v_i (non-conservative metric form
@@ -182,11 +195,7 @@ constexpr std::size_t kLdsBytes = 160 * 1024;
 // 64 x (TY+2H), the per-thread ring of QD planes of F_s; sigma (6) and M_s
 // (3) of planes a .. a+R, read once from memory as the s-flux lead and kept
 // until the plane is the output plane (when the budget allows it; otherwise
-// plane a reloads them); the closure rows (D+, D- and their mirror images);
-// the penalty coefficients of the tile's q faces (TY rows) and r faces (64
-// columns) for the current plane, loaded one plane ahead like the field data
-// (a wait for a load issued later than the prefetch would also wait for the
-// prefetch), when the budget allows it
+// plane a reloads them); the closure rows (D+, D- and their mirror images)
 template <typename T, int ORDER, int TY>
 struct StageLds {
   using S = Stencil<ORDER>;
@@ -194,17 +203,13 @@ struct StageLds {
   static constexpr int VX = 64 + 2 * H, VY = TY + 2 * H, QX = 64 + 2 * H, RX = 64;
   static constexpr int QD = R + Q + 1, SD = R + 1;
   static constexpr int TABN = kMaxM * kMaxCols;
-  static constexpr int NFQ = kNumFaceCoef * TY, NFR = kNumFaceCoef * 64, NFE = 2 * NFQ + 2 * NFR;
   static constexpr std::size_t n_lv = 3 * VX * VY, n_lq = 3 * QX * TY, n_lr = 3 * RX * VY, n_ring = QD * 3 * NT;
   static constexpr std::size_t base_bytes = sizeof(T) * (n_lv + n_lq + n_lr + n_ring);
   static constexpr bool SR = base_bytes + sizeof(T) * SD * 9 * NT <= kLdsBytes;
   static constexpr std::size_t n_sring = SR ? SD * 9 * NT : 1;
-  static constexpr bool FL = base_bytes + (SR ? sizeof(T) * SD * 9 * NT : 0) +
-                                 sizeof(T) * (kClosureTab * TABN + NFE) <= kLdsBytes;
-  static constexpr std::size_t n_tab = kClosureTab * TABN, n_face = FL ? NFE : 1;
+  static constexpr std::size_t n_tab = kClosureTab * TABN;
   static constexpr std::size_t o_lv = 0, o_lq = o_lv + n_lv, o_lr = o_lq + n_lq, o_ring = o_lr + n_lr,
-                               o_sring = o_ring + n_ring, o_tab = o_sring + n_sring, o_face = o_tab + n_tab,
-                               total = o_face + n_face;
+                               o_sring = o_ring + n_ring, o_tab = o_sring + n_sring, total = o_tab + n_tab;
   static constexpr std::size_t bytes = total * sizeof(T);
 };
 
@@ -233,11 +238,6 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   constexpr bool SR = L::SR;
   T* const sring = reinterpret_cast<T*>(lds) + L::o_sring;
   T* const ltab = reinterpret_cast<T*>(lds) + L::o_tab;
-  constexpr int NFQ = L::NFQ, NFR = L::NFR;
-  constexpr int NFE = L::NFE;
-  constexpr bool FL = L::FL;
-  constexpr int KF = FL ? (NFE + NT - 1) / NT : 1;
-  T* const lface = reinterpret_cast<T*>(lds) + L::o_face;
 
   if (tile >= A.ntiles) return;
   const int xt = tile % A.nxt;
@@ -358,64 +358,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   constexpr int NSG = SR ? 1 : 6, NMS = SR ? 6 : 9;
   T p_sg[NSG], p_m[NMS], p_mat[3], p_dq[9], p_hy[12], p_hx[12];
   const bool rdq = A.read_dq != 0;
-  // penalty coefficients of the tile's faces: lface entry e is face f,
-  // coefficient k, position pos along the face (row offset from y0 on the q
-  // faces, column offset from x0 on the r faces)
-  const bool fq0 = x0 == 0, fq1 = x1 == nq, fr0 = y0 == 0, fr1 = y1 == nr;
-  const bool anyface = FL && (fq0 || fq1 || fr0 || fr1);
-  auto face_src = [&](int e, int p, std::size_t& src) -> bool {
-    if (e < 2 * NFQ) {
-      const int f = e / NFQ, rem = e - f * NFQ, k = rem / TY, pos = rem - k * TY;
-      const int jj = y0 + pos;
-      if (!(f == 0 ? fq0 : fq1) || jj >= nr) return false;
-      const std::size_t fo = f == 0 ? A.face_off[0] : A.face_off[1];
-      const std::size_t fn = f == 0 ? A.face_n[0] : A.face_n[1];
-      src = fo + (std::size_t)p * nr + jj + (std::size_t)k * fn;
-      return true;
-    }
-    if (e < NFE) {
-      const int e2 = e - 2 * NFQ, g = e2 / NFR, rem = e2 - g * NFR, k = rem / 64, pos = rem - k * 64;
-      const int ii = x0 + pos;
-      if (!(g == 0 ? fr0 : fr1) || ii >= nq) return false;
-      const std::size_t fo = g == 0 ? A.face_off[2] : A.face_off[3];
-      const std::size_t fn = g == 0 ? A.face_n[2] : A.face_n[3];
-      src = fo + (std::size_t)p * nq + ii + (std::size_t)k * fn;
-      return true;
-    }
-    return false;
-  };
-  T p_face[KF];
-#pragma unroll
-  for (int u = 0; u < KF; ++u) p_face[u] = T(0);
-  auto load_plane = [&](int a) {
+  // the halo points of a plane are loaded with the plane's other data one
+  // plane ahead; in double precision their registers do not fit beside the
+  // rest, and each plane loads its halo points when it starts
+  constexpr bool HALO_AHEAD = sizeof(T) == 4;
+  auto load_halo = [&](int a) {
     const unsigned pa = (unsigned)a * plane;
-    // Every lane loads; a lane that needs no value reads element 0 of the
-    // plane (or of the array).  Loads under a mask or a branch would make the
-    // compiler merge old and new register values, and the merge waits for
-    // the loads in flight.
-    if constexpr (FL) {
-#pragma unroll
-      for (int u = 0; u < KF; ++u) {
-        std::size_t src = 0;
-        const bool need = anyface && face_src(tid + u * NT, a, src);
-        p_face[u] = A.face[need ? src : 0];
-      }
-    }
-    const unsigned oi = pa + (ing ? col : 0u);
-    const unsigned oa = pa + (act ? col : 0u);
-    if constexpr (!SR) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) p_sg[c] = gq.ld(3 + c, oi);
-#pragma unroll
-      for (int c = 6; c < 9; ++c) p_m[c] = gc.ld(c, oa);
-    }
-#pragma unroll
-    for (int c = 0; c < 6; ++c) p_m[c] = gc.ld(c, oi);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) p_mat[c] = gc.ldn(9 + c, oa);
-    const unsigned od = rdq ? oa : 0u;   // unused (and masked below) in the first stage
-#pragma unroll
-    for (int c = 0; c < 9; ++c) p_dq[c] = gd.ldn(c, od);
     const unsigned ohv = pa + (yh_v ? yh_col : 0u);
     const unsigned ohf = pa + (yh_f ? yh_col : 0u);
 #pragma unroll
@@ -432,6 +380,29 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
       for (int c = 0; c < 3; ++c) p_hx[9 + c] = gc.ld(c, ox);
     }
   };
+  auto load_plane = [&](int a) {
+    const unsigned pa = (unsigned)a * plane;
+    // Every lane loads; a lane that needs no value reads element 0 of the
+    // plane (or of the array).  Loads under a mask or a branch would make the
+    // compiler merge old and new register values, and the merge waits for
+    // the loads in flight.
+    const unsigned oi = pa + (ing ? col : 0u);
+    const unsigned oa = pa + (act ? col : 0u);
+    if constexpr (!SR) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) p_sg[c] = gq.ld(3 + c, oi);
+#pragma unroll
+      for (int c = 6; c < 9; ++c) p_m[c] = gc.ld(c, oa);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) p_m[c] = gc.ld(c, oi);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p_mat[c] = gc.ldn(9 + c, oa);
+    const unsigned od = rdq ? oa : 0u;   // unused (and masked below) in the first stage
+#pragma unroll
+    for (int c = 0; c < 9; ++c) p_dq[c] = gd.ldn(c, od);
+    if constexpr (HALO_AHEAD) load_halo(a);
+  };
 #pragma unroll
   for (int c = 0; c < NSG; ++c) p_sg[c] = T(0);
 #pragma unroll
@@ -445,12 +416,15 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   // results of the previous plane, stored after the next plane's loads have
   // been issued: loads and stores share one counter, and a wait for a load
   // while stores are in flight waits for the stores as well, so stores issued
-  // at the end of a plane would put one write round trip on every plane
-  T st_d[9], st_q[9];
+  // at the end of a plane would put one write round trip on every plane.  In
+  // double precision the 18 held values do not fit the register budget
+  // beside the prefetch: there each plane stores its results at once.
+  constexpr bool DEFER = sizeof(T) == 4;
+  T st_d[DEFER ? 9 : 1], st_q[DEFER ? 9 : 1];
   unsigned st_o = 0;
   bool st_pend = false;
   auto flush_stores = [&]() {
-    if (st_pend && act) {
+    if (DEFER && st_pend && act) {
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
         gd.st(c, st_o, st_d[c]);
@@ -462,6 +436,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   for (int a = z0; a < z1; ++a) {
     const unsigned pa = (unsigned)a * plane;
     const unsigned o = pa + col;
+    if constexpr (!HALO_AHEAD) load_halo(a);
     // ---------------- phase 1: stage plane a in LDS from the prefetched registers
     T sg[6], mq[3], mr[3], ms[3], dqo[9];
     if constexpr (SR) {
@@ -524,15 +499,6 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
       lq[1 * QX * TY + wq] = f[1];
       lq[2 * QX * TY + wq] = f[2];
     }
-    if constexpr (FL) {
-      if (anyface) {
-#pragma unroll
-        for (int u = 0; u < KF; ++u) {
-          const int e = tid + u * NT;
-          if (e < NFE) lface[e] = p_face[u];
-        }
-      }
-    }
     __syncthreads();
 
     // s-queue lead planes, then the prefetch of plane a+1.  The lead values
@@ -571,6 +537,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
           }
           u[0][c] = sp * ihq;
           dv[c] = -sm * ihq;
+          sched_fence<T>();
         }
       } else {
         T sp[3] = {T(0), T(0), T(0)}, sm[3] = {T(0), T(0), T(0)};
@@ -605,6 +572,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
           }
           u[1][c] = sp * ihr;
           dv[c] -= sm * ihr;
+          sched_fence<T>();
         }
       } else {
         T sp[3] = {T(0), T(0), T(0)}, sm[3] = {T(0), T(0), T(0)};
@@ -642,6 +610,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
           }
           u[2][c] = sp * ihs;
           dv[c] -= sm * ihs;
+          sched_fence<T>();
         }
       } else {
         const bool left = a < M;
@@ -673,56 +642,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
 
       const T v[3] = {vq[0][R], vq[1][R], vq[2][R]};
 
-      // boundary penalties (faces q0, q1, r0, r1, s0, s1)
-      if (A.sat && (i == 0 || i == nq - 1 || j == 0 || j == nr - 1 || a == 0 || a == ns - 1)) {
-        T fc[kNumFaceCoef];
-        // coefficients of face f at in-face index idx, from global memory
-        auto face_global = [&](int f, std::size_t idx) {
-#pragma unroll
-          for (int k = 0; k < kNumFaceCoef; ++k) fc[k] = A.face[A.face_off[f] + idx + (std::size_t)k * A.face_n[f]];
-        };
-        // q face f (0 or 1) and r face f (2 or 3) of the current plane
-        auto face_q = [&](int f) {
-          if constexpr (FL) {
-#pragma unroll
-            for (int k = 0; k < kNumFaceCoef; ++k) fc[k] = lface[f * NFQ + k * TY + ty];
-          } else {
-            face_global(f, (std::size_t)a * nr + j);
-          }
-        };
-        auto face_r = [&](int f) {
-          if constexpr (FL) {
-#pragma unroll
-            for (int k = 0; k < kNumFaceCoef; ++k) fc[k] = lface[2 * NFQ + (f - 2) * NFR + k * 64 + tx];
-          } else {
-            face_global(f, (std::size_t)a * nq + i);
-          }
-        };
-        if (i == 0) {
-          face_q(0);
-          face_penalty(fc, A.gamma[0], T(-1), A.traction[0], v, sg, rate);
-        }
-        if (i == nq - 1) {
-          face_q(1);
-          face_penalty(fc, A.gamma[1], T(1), A.traction[1], v, sg, rate);
-        }
-        if (j == 0) {
-          face_r(2);
-          face_penalty(fc, A.gamma[2], T(-1), A.traction[2], v, sg, rate);
-        }
-        if (j == nr - 1) {
-          face_r(3);
-          face_penalty(fc, A.gamma[3], T(1), A.traction[3], v, sg, rate);
-        }
-        if (a == 0) {
-          face_global(4, (std::size_t)j * nq + i);
-          face_penalty(fc, A.gamma[4], T(-1), A.traction[4], v, sg, rate);
-        }
-        if (a == ns - 1) {
-          face_global(5, (std::size_t)j * nq + i);
-          face_penalty(fc, A.gamma[5], T(1), A.traction[5], v, sg, rate);
-        }
-      }
+      // the boundary penalties of face nodes are added by penalty_kernel
+      // after the launch
 
       // Runge-Kutta stage update
       const T dt = A.dt, Ak = A.Ak, Bk = A.Bk;
@@ -730,8 +651,13 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
       for (int c = 0; c < 9; ++c) {
         const T d = dt * rate[c] + Ak * dqo[c];
         const T q0 = (c < 3) ? v[c] : sg[c - 3];
-        st_d[c] = d;
-        st_q[c] = q0 + Bk * d;
+        if constexpr (DEFER) {
+          st_d[c] = d;
+          st_q[c] = q0 + Bk * d;
+        } else {
+          gd.st(c, o, d);
+          go.st(c, o, q0 + Bk * d);
+        }
       }
       st_o = o;
     }
@@ -775,7 +701,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
 // every axis (always the case along the normal axis) gather their columns
 // from memory.  Same arithmetic as the stage kernel: interior rows from the
 // interior stencil, boundary rows from the closure table, fluxes by flux3,
-// rates by node_rates, penalties by face_penalty, then the Runge-Kutta update.
+// rates by node_rates, then the Runge-Kutta update (the penalties of its
+// face nodes follow in penalty_kernel).
 // LDS of edge_body<T, ORDER, KZ>: the closure rows, the patch (v, the
 // tangential flux and the s flux of 64 + 2H strip points x KZ + 2H planes)
 // and, for the column strip, the partial sums of its q closure row over
@@ -1013,20 +940,7 @@ __device__ __forceinline__ void edge_body(const StageArgs<T>& A, int b, char* ld
   T rate[9];
   node_rates(u, dv, mq, mr, ms, cf[9 * field + o], cf[10 * field + o], cf[11 * field + o], rate);
 
-  if (A.sat && (i == 0 || i == nq - 1 || j == 0 || j == nr - 1 || k == 0 || k == ns - 1)) {
-    T fc[kNumFaceCoef];
-    auto face = [&](int f, std::size_t idx, T eps) {
-#pragma unroll
-      for (int kk = 0; kk < kNumFaceCoef; ++kk) fc[kk] = A.face[A.face_off[f] + idx + (std::size_t)kk * A.face_n[f]];
-      face_penalty(fc, A.gamma[f], eps, A.traction[f], v, sg, rate);
-    };
-    if (i == 0) face(0, (std::size_t)k * nr + j, T(-1));
-    if (i == nq - 1) face(1, (std::size_t)k * nr + j, T(1));
-    if (j == 0) face(2, (std::size_t)k * nq + i, T(-1));
-    if (j == nr - 1) face(3, (std::size_t)k * nq + i, T(1));
-    if (k == 0) face(4, (std::size_t)j * nq + i, T(-1));
-    if (k == ns - 1) face(5, (std::size_t)j * nq + i, T(1));
-  }
+  // the boundary penalties are added by penalty_kernel after the launch
 
   const T dt = A.dt, Ak = A.Ak, Bk = A.Bk;
 #pragma unroll
@@ -1150,6 +1064,79 @@ __global__ __launch_bounds__(512, SBP_STAGE_MIN_WAVES) void stage_kernel_worklis
   const BatchItem w = P.items[item];
   const StageArgs<T> A = P.args[w.grid];
   persist_dispatch<T, MASK, PersistOrders<T>::hi>(A, w, lds);
+}
+
+// ---------------------------------------------------------------------------
+// Boundary penalties: one thread per node of the block's surface, which is
+// enumerated once: the q faces (all j, k), the r faces (interior i, all k),
+// the s faces (interior i and j).  Each node sums the penalties of every face
+// it lies on, in the face order (q0, q1, r0, r1, s0, s1), and adds them to
+// the stage update: dQ += dt P, Q_out += B_k dt P (Q_in is the stage input).
+template <typename T>
+__device__ __forceinline__ void penalty_body(const StageArgs<T>& A, long long e) {
+  const int nq = A.nq, nr = A.nr, ns = A.ns;
+  const long long nA = 2LL * nr * ns, nB = 2LL * (nq - 2) * ns, nC = 2LL * (nq - 2) * (nr - 2);
+  int i, j, k;
+  if (e < nA) {
+    const long long per = (long long)nr * ns, r = e % per;
+    i = e < per ? 0 : nq - 1;
+    j = (int)(r % nr);
+    k = (int)(r / nr);
+  } else if ((e -= nA) < nB) {
+    const long long per = (long long)(nq - 2) * ns, r = e % per;
+    j = e < per ? 0 : nr - 1;
+    i = 1 + (int)(r % (nq - 2));
+    k = (int)(r / (nq - 2));
+  } else if ((e -= nB) < nC) {
+    const long long per = (long long)(nq - 2) * (nr - 2), r = e % per;
+    k = e < per ? 0 : ns - 1;
+    i = 1 + (int)(r % (nq - 2));
+    j = 1 + (int)(r / (nq - 2));
+  } else {
+    return;
+  }
+  const long long o = A.nm(i, j, k);
+  const std::size_t field = A.field;
+  T v[3], sg[6], rate[9];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) v[c] = A.qin[c * field + o];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) sg[c] = A.qin[(3 + c) * field + o];
+#pragma unroll
+  for (int c = 0; c < 9; ++c) rate[c] = T(0);
+  T fc[kNumFaceCoef];
+  auto face = [&](int f, std::size_t idx, T eps) {
+#pragma unroll
+    for (int kk = 0; kk < kNumFaceCoef; ++kk) fc[kk] = A.face[A.face_off[f] + idx + (std::size_t)kk * A.face_n[f]];
+    face_penalty(fc, A.gamma[f], eps, A.traction[f], v, sg, rate);
+  };
+  if (i == 0) face(0, (std::size_t)k * nr + j, T(-1));
+  if (i == nq - 1) face(1, (std::size_t)k * nr + j, T(1));
+  if (j == 0) face(2, (std::size_t)k * nq + i, T(-1));
+  if (j == nr - 1) face(3, (std::size_t)k * nq + i, T(1));
+  if (k == 0) face(4, (std::size_t)j * nq + i, T(-1));
+  if (k == ns - 1) face(5, (std::size_t)j * nq + i, T(1));
+  const T dt = A.dt, Bk = A.Bk;
+#pragma unroll
+  for (int c = 0; c < 9; ++c) {
+    const T d = dt * rate[c];
+    A.dq[c * field + o] += d;
+    A.qout[c * field + o] += Bk * d;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void penalty_kernel(const StageArgs<T> A) {
+  penalty_body(A, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// surface nodes of several grids: thread -> grid by the prefix sums in first
+template <typename T>
+__global__ __launch_bounds__(256) void penalty_kernel_batch(const BatchArgs<T> B) {
+  const int item = blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= B.total) return;
+  const int g = batch_find(B.first, B.n, item);
+  penalty_body(B.args[g], item - B.first[g]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1430,6 +1417,20 @@ bool worklist_order_ok(int order) {
 }
 
 template <typename T>
+hipError_t launch_penalty(const StageArgs<T>& a, hipStream_t st) {
+  const long long n = surface_nodes(a.nq, a.nr, a.ns);
+  hipLaunchKernelGGL(penalty_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_penalty_batch(const BatchArgs<T>& b, hipStream_t st) {
+  if (b.total == 0) return hipSuccess;
+  hipLaunchKernelGGL(penalty_kernel_batch<T>, dim3((b.total + 255) / 256), dim3(256), 0, st, b);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_source(const SourceArgs<T>& s, int nsrc, hipStream_t st) {
   hipLaunchKernelGGL(source_kernel<T>, dim3(nsrc), dim3(256), 0, st, s);
   return hipGetLastError();
@@ -1476,6 +1477,10 @@ template hipError_t launch_stage_worklist<float>(const PersistArgs<float>&, unsi
 template hipError_t launch_stage_worklist<double>(const PersistArgs<double>&, unsigned, int, hipStream_t);
 template bool worklist_order_ok<float>(int);
 template bool worklist_order_ok<double>(int);
+template hipError_t launch_penalty<float>(const StageArgs<float>&, hipStream_t);
+template hipError_t launch_penalty<double>(const StageArgs<double>&, hipStream_t);
+template hipError_t launch_penalty_batch<float>(const BatchArgs<float>&, hipStream_t);
+template hipError_t launch_penalty_batch<double>(const BatchArgs<double>&, hipStream_t);
 template hipError_t launch_source<float>(const SourceArgs<float>&, int, hipStream_t);
 template hipError_t launch_source<double>(const SourceArgs<double>&, int, hipStream_t);
 template hipError_t launch_record<float>(const float*, std::size_t, const long long*, int, float*,

@@ -26,7 +26,7 @@ struct StageArgs {
   int ncol;
   int read_dq;
   int ex, ey;         // edge kernel: last q column / last r row
-  int sat;            // 1: boundary penalties on; 0: volume terms only
+  int sat;            // 1: boundary penalties follow (launch_penalty); 0: volume terms only
   int plain;          // 1: plain pointers even where buffer addressing fits
   int traction[6];
   T Ak, Bk, dt;
@@ -160,6 +160,18 @@ template <typename T>
 bool worklist_order_ok(int order);
 template <typename T>
 hipError_t launch_record_batch(const RecordBatch<T>& b, hipStream_t st);
+// boundary penalties of the block's surface nodes, added to dQ and Q_out
+// after the stage and edge kernels
+template <typename T>
+hipError_t launch_penalty(const StageArgs<T>& a, hipStream_t st);
+// the same for several grids: b.first holds the prefix sums of their
+// surface node counts (surface_nodes)
+template <typename T>
+hipError_t launch_penalty_batch(const BatchArgs<T>& b, hipStream_t st);
+// nodes of the block's surface (each once)
+__host__ __device__ inline long long surface_nodes(int nq, int nr, int ns) {
+  return 2LL * nr * ns + 2LL * (nq - 2) * ns + 2LL * (nq - 2) * (nr - 2);
+}
 template <typename T>
 hipError_t launch_source(const SourceArgs<T>& s, int nsrc, hipStream_t st);
 template <typename T>
