@@ -193,10 +193,12 @@ int sbp_record(sbp_handle h, int nrec, const int* ijk, void* out_device, int max
  * dQ <- A_k dQ + dt RHS, Q <- Q + B_k dQ.  Asynchronous on the stream.
  * SBP_ESTATE before sbp_set_material.
  * The call's first step is issued as direct launches (five stages of
- * stage, edge and source kernels, the receivers, a clock tick); every later
- * step is one replay of a HIP graph holding the same launches, captured on
- * first use and again whenever dt, the sources, the receivers or the launch
- * shape change.  The per-step values (the source-time factor
+ * stage, edge, penalty and source kernels, the receivers, a clock tick);
+ * every later step is one replay of a HIP graph holding the same launches,
+ * captured on first use and again whenever dt, the sources, the receivers or
+ * the launch shape change -- when none of the step's kernels uses scratch
+ * memory (register spills; the SBP_F32 kernels); otherwise every step is
+ * issued directly.  The per-step values (the source-time factor
  * dt g(t_n + C_k dt) of every stage, evaluated on the host in double, and
  * the receiver slot) are read from a device table and a device step
  * counter, uploaded / set once per 512 steps.
@@ -204,9 +206,10 @@ int sbp_record(sbp_handle h, int nrec, const int* ijk, void* out_device, int max
 int sbp_step(sbp_handle h, int nsteps, double dt);
 
 /*
- * on = 1 (default): sbp_step replays captured step graphs; on = 0: it
- * issues the same launches one by one.  Results are bitwise identical.
- * Profiling (sbp_set_profiling) uses the one-by-one launches.
+ * on = 1 (default): sbp_step and sbp_step_batch replay captured step graphs
+ * where their kernels use no scratch memory; on = 0: they issue the same
+ * launches one by one.  Results are bitwise identical.  Profiling
+ * (sbp_set_profiling) uses the one-by-one launches.
  */
 int sbp_set_graphs(sbp_handle h, int on);
 
@@ -218,9 +221,10 @@ int sbp_set_graphs(sbp_handle h, int on);
  * stage-kernel tiles and edge-kernel blocks of every handle, split into one
  * segment per XCD of equal estimated cost, longest items first (block b of
  * the launch runs item b / 8 of segment b % 8); then one launch injects
- * every point source; per step one launch records every receiver.  In
- * SBP_F32 each step is a replay of a graph captured for the call (even and
- * odd steps); in SBP_F64 the same launches are issued directly.  The
+ * every point source; per step one launch records every receiver.  Where
+ * the kernels use no scratch memory (SBP_F32) each step is a replay of a
+ * graph captured for the call (even and odd steps); otherwise the same
+ * launches are issued directly.  The
  * source-time factors come from a device table uploaded every 64 steps.
  * Every grid uses
  * 8-row tiles and one s-chunk length for the batch (from

@@ -665,7 +665,9 @@ int do_steps(sbp_ctx* h, int nsteps, double dt) {
   StageArgs<T> a = stage_args<T>(h);
   StepClock* clk = (StepClock*)(h->ws + h->off_clock);
   const double t0 = h->t;
-  const bool use_graph = h->graphs && !h->prof;
+  // graphs replay only steps whose kernels use no scratch memory (see
+  // DESIGN: graph-replayed double-precision kernels that spill went wrong)
+  const bool use_graph = h->graphs && !h->prof && step_scratch<T>(h->order, h->ty) == 0;
   for (int n0 = 0; n0 < nsteps; n0 += kTabSteps) {
     const int nc = std::min(kTabSteps, nsteps - n0);
     const int part = h->tab_next;
@@ -1108,10 +1110,10 @@ int do_steps_batch(sbp_ctx** hs, int n, int nsteps, const double* dt) {
         if (g[i]) (void)hipGraphExecDestroy(g[i]);
     }
   } drop{gx};
-  // FP32 batches replay captured step graphs; FP64 batches issue the same
-  // launches directly (their kernel bodies keep part of their state in
-  // scratch memory; see DESIGN: a graph-replayed FP64 batch went wrong)
-  const bool use_graph = h0->graphs && sizeof(T) == 4;
+  // graphs replay only batched steps whose kernels use no scratch memory
+  // (the FP32 kernels; see DESIGN: graph-replayed double-precision kernels
+  // that spill went wrong)
+  const bool use_graph = h0->graphs && P.worklist && batch_step_scratch<T>(P.orders) == 0;
   if (use_graph) {
     if (!h0->cap) HIPCHK(hipStreamCreateWithFlags(&h0->cap, hipStreamNonBlocking));
     for (int par = 0; par < 2 && par < nsteps; ++par) {

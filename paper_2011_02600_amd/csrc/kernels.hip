@@ -200,16 +200,25 @@ template <typename T, int ORDER, int TY>
 struct StageLds {
   using S = Stencil<ORDER>;
   static constexpr int R = S::R, Q = S::Q, H = Q, NT = 64 * TY;
-  static constexpr int VX = 64 + 2 * H, VY = TY + 2 * H, QX = 64 + 2 * H, RX = 64;
   static constexpr int QD = R + Q + 1, SD = R + 1;
+  // q derivatives: every lane sums NC = M + Q taps (a closure row's width;
+  // the interior stencil padded with zero weights), so the windows along q
+  // hold NC - QD zero columns beyond the halo
+  static constexpr int NC = S::M + S::Q, PADQ = NC - QD;
+  static constexpr int VX = 64 + 2 * H + PADQ, VY = TY + 2 * H, QX = 64 + 2 * H + PADQ, RX = 64;
   static constexpr int TABN = kMaxM * kMaxCols;
+  // rows of q weights: interior, left closure rows 0..M-1, right closure rows
+  // 0..M-1 (columns nq-NC .. nq-1 ascending); D+ rows, then D- rows
+  static constexpr int QROWS = 2 * S::M + 1;
+  static constexpr std::size_t n_tq = 2 * QROWS * NC;
   static constexpr std::size_t n_lv = 3 * VX * VY, n_lq = 3 * QX * TY, n_lr = 3 * RX * VY, n_ring = QD * 3 * NT;
   static constexpr std::size_t base_bytes = sizeof(T) * (n_lv + n_lq + n_lr + n_ring);
   static constexpr bool SR = base_bytes + sizeof(T) * SD * 9 * NT <= kLdsBytes;
   static constexpr std::size_t n_sring = SR ? SD * 9 * NT : 1;
   static constexpr std::size_t n_tab = kClosureTab * TABN;
   static constexpr std::size_t o_lv = 0, o_lq = o_lv + n_lv, o_lr = o_lq + n_lq, o_ring = o_lr + n_lr,
-                               o_sring = o_ring + n_ring, o_tab = o_sring + n_sring, total = o_tab + n_tab;
+                               o_sring = o_ring + n_ring, o_tab = o_sring + n_sring, o_tq = o_tab + n_tab,
+                               total = o_tq + n_tq;
   static constexpr std::size_t bytes = total * sizeof(T);
 };
 
@@ -238,6 +247,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   constexpr bool SR = L::SR;
   T* const sring = reinterpret_cast<T*>(lds) + L::o_sring;
   T* const ltab = reinterpret_cast<T*>(lds) + L::o_tab;
+  T* const tq = reinterpret_cast<T*>(lds) + L::o_tq;
+  constexpr int NC = L::NC, QROWS = L::QROWS;
 
   if (tile >= A.ntiles) return;
   const int xt = tile % A.nxt;
@@ -262,6 +273,23 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
 
   const Arr<T, BUF> gq(A.qin, field), gc(A.coef, field), gd(A.dq, field), go(A.qout, field);
   for (int e = threadIdx.y * 64 + threadIdx.x; e < kClosureTab * TABN; e += NT) ltab[e] = A.tab[e];
+  // the q weight rows (from the closure table in memory, the right-end rows
+  // reversed so that every row runs over ascending columns; D- interior
+  // weights with the sign of the difference folded in) and zeroed q windows
+  for (int e = threadIdx.y * 64 + threadIdx.x; e < 2 * QROWS * NC; e += NT) {
+    const int pm = e / (QROWS * NC), rem = e - pm * QROWS * NC, row = rem / NC, t = rem - row * NC;
+    T w = T(0);
+    if (row == 0) {
+      if (t < QD) w = pm == 0 ? T(S::a[t]) : -T(S::a[R + Q - t]);
+    } else if (row <= M) {
+      w = A.tab[pm * TABN + (row - 1) * kMaxCols + t];
+    } else {
+      w = A.tab[(2 + pm) * TABN + (row - 1 - M) * kMaxCols + (NC - 1 - t)];
+    }
+    tq[e] = w;
+  }
+  for (int e = threadIdx.y * 64 + threadIdx.x; e < 3 * VX * VY; e += NT) lv[e] = T(0);
+  for (int e = threadIdx.y * 64 + threadIdx.x; e < 3 * QX * TY; e += NT) lq[e] = T(0);
 
   // y halo: rows y0-H..y0-1 and y0+TY..y0+TY+H-1, columns x0..x1-1
   const int yh_r = tid >> 6;
@@ -341,13 +369,25 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
 
   const int vme = (ty + H) * VX + tx + H;   // own position in the v window
   const int qme = ty * QX + tx + H;         // ... F_q window
+  // q weight row of the lane and the window columns its taps start at
+  const int qrow = (i < M) ? 1 + i : (i >= nq - M ? 1 + M + (nq - 1 - i) : 0);
+  const int qv0 = (ty + H) * VX + (qrow == 0 ? tx + H - R : (i < M ? H - x0 : H - x0 + nq - NC));
+  const int qf0 = ty * QX + (qrow == 0 ? tx + H - Q : (i < M ? H - x0 : H - x0 + nq - NC));
+  // FP32 keeps the lane's weights in registers; FP64 reads them from LDS
+  constexpr bool QWREG = sizeof(T) == 4;
+  T wqp[QWREG ? NC : 1], wqm[QWREG ? NC : 1];
+  __syncthreads();  // weight rows written, windows zeroed
+  if constexpr (QWREG) {
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+      wqp[t] = tq[qrow * NC + t];
+      wqm[t] = tq[(QROWS + qrow) * NC + t];
+    }
+  }
   const int rme = (ty + H) * RX + tx;       // ... F_r window
   const T ihq = A.inv_h[0], ihr = A.inv_h[1], ihs = A.inv_h[2];
-  const bool xin = i >= M && i < nq - M;
   const bool yin = j >= M && j < nr - M;
-  const int xrow = (i < M) ? i : nq - 1 - i;
   const int yrow = (j < M) ? j : nr - 1 - j;
-  const int xtab = (i < M) ? 0 : 2 * TABN;   // closure rows in ltab
   const int ytab = (j < M) ? 0 : 2 * TABN;
   const int ncol = A.ncol;
 
@@ -525,40 +565,21 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
     if (act) {
       T u[3][3];   // u[xi][c] = D+_xi v_c
       T dv[3];     // sum_xi D-_xi F_xi,c
-      // q direction
-      if (__builtin_expect(xin, 1)) {
+      // q direction: the same NC taps for interior and closure lanes (no
+      // divergence within a wave); zero weights on the padding taps
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          T sp = T(0), sm = T(0);
+      for (int c = 0; c < 3; ++c) {
+        T sp = T(0), sm = T(0);
 #pragma unroll
-          for (int s = 0; s < QD; ++s) {
-            sp += T(S::a[s]) * lv[c * VX * VY + vme - R + s];
-            sm += T(S::a[s]) * lq[c * QX * TY + qme + R - s];
-          }
-          u[0][c] = sp * ihq;
-          dv[c] = -sm * ihq;
-          sched_fence<T>();
+        for (int t = 0; t < NC; ++t) {
+          const T cp = QWREG ? wqp[QWREG ? t : 0] : tq[qrow * NC + t];
+          const T cm = QWREG ? wqm[QWREG ? t : 0] : tq[(QROWS + qrow) * NC + t];
+          sp += cp * lv[c * VX * VY + qv0 + t];
+          sm += cm * lq[c * QX * TY + qf0 + t];
         }
-      } else {
-        T sp[3] = {T(0), T(0), T(0)}, sm[3] = {T(0), T(0), T(0)};
-        const bool left = i < M;
-        const int gv = (ty + H) * VX + H - x0 + (left ? 0 : nq - 1);
-        const int gq = ty * QX + H - x0 + (left ? 0 : nq - 1);
-        const int step = left ? 1 : -1;
-        for (int cc = 0; cc < ncol; ++cc) {
-          const T cp = ltab[xtab + xrow * kMaxCols + cc];
-          const T cm = ltab[xtab + TABN + xrow * kMaxCols + cc];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            sp[c] += cp * lv[c * VX * VY + gv + step * cc];
-            sm[c] += cm * lq[c * QX * TY + gq + step * cc];
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          u[0][c] = sp[c] * ihq;
-          dv[c] = sm[c] * ihq;
-        }
+        u[0][c] = sp * ihq;
+        dv[c] = sm * ihq;
+        sched_fence<T>();
       }
       // r direction
       if (__builtin_expect(yin, 1)) {
@@ -737,6 +758,10 @@ __device__ __forceinline__ void edge_body(const StageArgs<T>& A, int b, char* ld
   const int ex = A.ex, ey = A.ey;
   const int tid = threadIdx.y * 64 + threadIdx.x;
   for (int e = tid; e < kClosureTab * TABN; e += NT) ltab[e] = A.tab[e];
+  // the column strip's partial sums below read the table: every wave's part
+  // of it must be written first (what an earlier block left in this LDS is
+  // another layout's data when blocks of several orders share the launch)
+  __syncthreads();
 
   // block -> strip, tangential tile, s tile
   const int nkt = (ns + KZ - 1) / KZ;
@@ -1293,6 +1318,74 @@ hipError_t launch_stage(int order, int ty, const StageArgs<T>& a, hipStream_t st
   return hipErrorInvalidValue;
 }
 
+// largest private (scratch) segment, bytes per lane, of the kernels one
+// step of `order` launches (stage kernel of tile height ty in both
+// addressings, edge, penalty, source and receiver kernels)
+template <typename T, int ORDER, int TY>
+static std::size_t step_scratch_t() {
+  if constexpr (sizeof(T) == 8 && (TY == 16 || ORDER == 7)) {
+    return 0;
+  } else {
+    std::size_t m = 0;
+    const void* fns[] = {reinterpret_cast<const void*>(&stage_kernel<T, ORDER, TY, true>),
+                         reinterpret_cast<const void*>(&stage_kernel<T, ORDER, TY, false>),
+                         reinterpret_cast<const void*>(&edge_kernel<T, ORDER, 8>),
+                         reinterpret_cast<const void*>(&penalty_kernel<T>),
+                         reinterpret_cast<const void*>(&source_kernel<T>),
+                         reinterpret_cast<const void*>(&record_kernel<T>)};
+    for (const void* f : fns) {
+      hipFuncAttributes at{};
+      if (hipFuncGetAttributes(&at, f) != hipSuccess) return (std::size_t)-1;
+      m = std::max<std::size_t>(m, at.localSizeBytes);
+    }
+    return m;
+  }
+}
+
+template <typename T>
+std::size_t step_scratch(int order, int ty) {
+  if (ty == 16 && sizeof(T) == 4) {
+    if (order == 2) return step_scratch_t<T, 2, 16>();
+    if (order == 3) return step_scratch_t<T, 3, 16>();
+    if (order == 4) return step_scratch_t<T, 4, 16>();
+    if (order == 5) return step_scratch_t<T, 5, 16>();
+    if (order == 6) return step_scratch_t<T, 6, 16>();
+    if (order == 7) return step_scratch_t<T, 7, 16>();
+  } else {
+    if (order == 2) return step_scratch_t<T, 2, 8>();
+    if (order == 3) return step_scratch_t<T, 3, 8>();
+    if (order == 4) return step_scratch_t<T, 4, 8>();
+    if (order == 5) return step_scratch_t<T, 5, 8>();
+    if (order == 6) return step_scratch_t<T, 6, 8>();
+    if (order == 7) return step_scratch_t<T, 7, 8>();
+  }
+  return (std::size_t)-1;
+}
+
+// the same for the batched step's kernels (work-list stage kernel for the
+// set of orders, penalty, source and receiver kernels)
+template <typename T>
+std::size_t batch_step_scratch(unsigned orders) {
+  constexpr unsigned kAll = ((1u << (PersistOrders<T>::hi + 1)) - 1) & ~3u;
+  const void* st = nullptr;
+  if ((orders & ~(1u << 4)) == 0) st = reinterpret_cast<const void*>(&stage_kernel_worklist<T, 1u << 4>);
+  else if ((orders & ~(1u << 6)) == 0) st = reinterpret_cast<const void*>(&stage_kernel_worklist<T, 1u << 6>);
+  else if ((orders & ~((1u << 4) | (1u << 6))) == 0)
+    st = reinterpret_cast<const void*>(&stage_kernel_worklist<T, (1u << 4) | (1u << 6)>);
+  else if ((orders & ~kAll) == 0) st = reinterpret_cast<const void*>(&stage_kernel_worklist<T, kAll>);
+  if (!st) return (std::size_t)-1;
+  std::size_t m = 0;
+  const void* fns[] = {st, reinterpret_cast<const void*>(&penalty_kernel_batch<T>),
+                       reinterpret_cast<const void*>(&source_kernel_batch<T>),
+                       reinterpret_cast<const void*>(&record_kernel_batch<T>)};
+  for (const void* f : fns) {
+    hipFuncAttributes at{};
+    if (hipFuncGetAttributes(&at, f) != hipSuccess) return (std::size_t)-1;
+    m = std::max<std::size_t>(m, at.localSizeBytes);
+  }
+  return m;
+}
+
 template <typename T>
 int edge_blocks(const StageArgs<T>& a) {
   constexpr int KZ = 8;
@@ -1463,6 +1556,10 @@ template hipError_t launch_stage<float>(int, int, const StageArgs<float>&, hipSt
 template hipError_t launch_stage<double>(int, int, const StageArgs<double>&, hipStream_t);
 template hipError_t launch_edge<float>(int, const StageArgs<float>&, hipStream_t);
 template hipError_t launch_edge<double>(int, const StageArgs<double>&, hipStream_t);
+template std::size_t step_scratch<float>(int, int);
+template std::size_t step_scratch<double>(int, int);
+template std::size_t batch_step_scratch<float>(unsigned);
+template std::size_t batch_step_scratch<double>(unsigned);
 template int edge_blocks<float>(const StageArgs<float>&);
 template int edge_blocks<double>(const StageArgs<double>&);
 template hipError_t launch_stage_batch<float>(int, int, const BatchArgs<float>&, bool, hipStream_t);

@@ -147,6 +147,12 @@ template <typename T>
 hipError_t launch_stage_batch(int order, int ty, const BatchArgs<T>& b, bool buf, hipStream_t st);
 template <typename T>
 int edge_blocks(const StageArgs<T>& a);
+// largest scratch (private segment) size, bytes per lane, of the kernels one
+// step launches; (size_t)-1 if it cannot be queried
+template <typename T>
+std::size_t step_scratch(int order, int ty);
+template <typename T>
+std::size_t batch_step_scratch(unsigned orders);
 template <typename T>
 hipError_t launch_edge_batch(int order, const BatchArgs<T>& b, hipStream_t st);
 template <typename T>
