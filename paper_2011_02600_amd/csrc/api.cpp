@@ -665,8 +665,10 @@ int do_steps(sbp_ctx* h, int nsteps, double dt) {
   StageArgs<T> a = stage_args<T>(h);
   StepClock* clk = (StepClock*)(h->ws + h->off_clock);
   const double t0 = h->t;
-  // graphs replay only steps whose kernels use no scratch memory (see
-  // DESIGN: graph-replayed double-precision kernels that spill went wrong)
+  // graphs replay only steps whose kernels use no scratch memory (a
+  // graph-launched double-precision kernel with a large private segment
+  // once ended in a memory fault whose cause was not found; kernels that
+  // spill launch eagerly)
   const bool use_graph = h->graphs && !h->prof && step_scratch<T>(h->order, h->ty) == 0;
   for (int n0 = 0; n0 < nsteps; n0 += kTabSteps) {
     const int nc = std::min(kTabSteps, nsteps - n0);
@@ -1111,8 +1113,7 @@ int do_steps_batch(sbp_ctx** hs, int n, int nsteps, const double* dt) {
     }
   } drop{gx};
   // graphs replay only batched steps whose kernels use no scratch memory
-  // (the FP32 kernels; see DESIGN: graph-replayed double-precision kernels
-  // that spill went wrong)
+  // (the FP32 kernels), as in do_steps
   const bool use_graph = h0->graphs && P.worklist && batch_step_scratch<T>(P.orders) == 0;
   if (use_graph) {
     if (!h0->cap) HIPCHK(hipStreamCreateWithFlags(&h0->cap, hipStreamNonBlocking));

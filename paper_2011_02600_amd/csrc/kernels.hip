@@ -402,6 +402,11 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   // plane ahead; in double precision their registers do not fit beside the
   // rest, and each plane loads its halo points when it starts
   constexpr bool HALO_AHEAD = sizeof(T) == 4;
+  // the material and the Runge-Kutta register are needed only by the stage
+  // update at the end of the plane: in double precision they are loaded when
+  // the plane starts (their latency hidden by the derivatives), not a plane
+  // ahead, which would keep two planes' copies live through the derivatives
+  constexpr bool LATE_AHEAD = sizeof(T) == 4;
   auto load_halo = [&](int a) {
     const unsigned pa = (unsigned)a * plane;
     const unsigned ohv = pa + (yh_v ? yh_col : 0u);
@@ -420,6 +425,15 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
       for (int c = 0; c < 3; ++c) p_hx[9 + c] = gc.ld(c, ox);
     }
   };
+  auto load_late = [&](int a) {
+    const unsigned pa = (unsigned)a * plane;
+    const unsigned oa = pa + (act ? col : 0u);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) p_mat[c] = gc.ldn(9 + c, oa);
+    const unsigned od = rdq ? oa : 0u;   // unused (and masked below) in the first stage
+#pragma unroll
+    for (int c = 0; c < 9; ++c) p_dq[c] = gd.ldn(c, od);
+  };
   auto load_plane = [&](int a) {
     const unsigned pa = (unsigned)a * plane;
     // Every lane loads; a lane that needs no value reads element 0 of the
@@ -436,11 +450,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
     }
 #pragma unroll
     for (int c = 0; c < 6; ++c) p_m[c] = gc.ld(c, oi);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) p_mat[c] = gc.ldn(9 + c, oa);
-    const unsigned od = rdq ? oa : 0u;   // unused (and masked below) in the first stage
-#pragma unroll
-    for (int c = 0; c < 9; ++c) p_dq[c] = gd.ldn(c, od);
+    if constexpr (LATE_AHEAD) load_late(a);
     if constexpr (HALO_AHEAD) load_halo(a);
   };
 #pragma unroll
@@ -477,6 +487,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
     const unsigned pa = (unsigned)a * plane;
     const unsigned o = pa + col;
     if constexpr (!HALO_AHEAD) load_halo(a);
+    if constexpr (!LATE_AHEAD) load_late(a);
     // ---------------- phase 1: stage plane a in LDS from the prefetched registers
     T sg[6], mq[3], mr[3], ms[3], dqo[9];
     if constexpr (SR) {
@@ -493,9 +504,14 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) { mq[c] = p_m[c]; mr[c] = p_m[3 + c]; }
+    T lamJ = T(0), muJ = T(0), rJ = T(0);
+    if constexpr (LATE_AHEAD) {  // copies before the prefetch of plane a + 1
 #pragma unroll
-    for (int c = 0; c < 9; ++c) dqo[c] = rdq ? p_dq[c] : T(0);
-    const T lamJ = p_mat[0], muJ = p_mat[1], rJ = p_mat[2];
+      for (int c = 0; c < 9; ++c) dqo[c] = rdq ? p_dq[c] : T(0);
+      lamJ = p_mat[0];
+      muJ = p_mat[1];
+      rJ = p_mat[2];
+    }
     if (ing) {
       lv[0 * VX * VY + vme] = vq[0][R];
       lv[1 * VX * VY + vme] = vq[1][R];
@@ -658,6 +674,13 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
         }
       }
 
+      if constexpr (!LATE_AHEAD) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) dqo[c] = rdq ? p_dq[c] : T(0);
+        lamJ = p_mat[0];
+        muJ = p_mat[1];
+        rJ = p_mat[2];
+      }
       T rate[9];
       node_rates(u, dv, mq, mr, ms, lamJ, muJ, rJ, rate);
 
@@ -779,10 +802,21 @@ __device__ __forceinline__ void edge_body(const StageArgs<T>& A, int b, char* ld
   const int mt = st == 0 ? 3 : 0;                         // metric row of the tangential axis
   const int mn = st == 0 ? 0 : 3;                         // metric row of the normal axis
   const long long field = (long long)A.field;
-  const NodeMap nm = A.nm;
+  // the node map's fields as scalars, both offsets formed before the
+  // select: a select between the fields of a local NodeMap (or a closure
+  // holding them) becomes a select of their addresses and keeps the object
+  // in scratch memory
+  const long long nm_plane = A.nm.plane, nm_cbase = A.nm.cbase;
+  const int nm_px = A.nm.px, nm_nr = A.nm.nr, nm_nqm = A.nm.nqm;
+  auto nm = [&](int i, int j, int k) -> long long {
+    const long long in = (long long)k * nm_plane + (long long)j * nm_px + i;
+    const long long last = nm_cbase + (long long)k * nm_nr + j;
+    return i < nm_nqm ? in : last;
+  };
   // element offset of the point (tangential t, s k) displaced dn along the normal axis
   auto at = [&](int dn, int t, int k) -> long long {
-    return st == 0 ? nm(nq - 1 + dn, t, k) : nm(t, nr - 1 + dn, k);
+    const int i = st == 0 ? nq - 1 + dn : t, j = st == 0 ? t : nr - 1 + dn;
+    return nm(i, j, k);
   };
   const T iht = st == 0 ? A.inv_h[1] : A.inv_h[0];
   const T ihn = st == 0 ? A.inv_h[0] : A.inv_h[1];
@@ -884,7 +918,10 @@ __device__ __forceinline__ void edge_body(const StageArgs<T>& A, int b, char* ld
       const bool left = p < M;
       const int row = left ? p : n - 1 - p;
       const int tb = left ? 0 : 2 * TABN;
-#pragma unroll
+      // in double precision a fully unrolled row keeps every column's loads
+      // in flight at once, more registers than the kernel has
+      constexpr int CU = sizeof(T) == 4 ? NC : 2;
+#pragma unroll CU
       for (int cc = 0; cc < NC; ++cc) {
         const int d = (left ? cc : n - 1 - cc) - p;
         const T cp = ltab[tb + row * kMaxCols + cc];
