@@ -935,7 +935,7 @@ int batch_upload(sbp_ctx** hs, int n, const double* dt, bool rhs_only, BatchPlan
     std::vector<int> pfirst(n + 1, 0);
     for (int q = 0; q < n; ++q) {
       const sbp_ctx* h = hs[P.worklist ? q : P.ord[q]];
-      pfirst[q + 1] = pfirst[q] + (int)surface_nodes(h->g.nq, h->g.nr, h->g.ns);
+      pfirst[q + 1] = pfirst[q] + (int)surface_nodes(h->g.nq, h->g.nr, h->g.ns, q0_in_stage<T>());
     }
     P.npen = pfirst[n];
     HIPCHK(hipMemcpyAsync(base + R.pen_first, pfirst.data(), pfirst.size() * sizeof(int), hipMemcpyHostToDevice, st));

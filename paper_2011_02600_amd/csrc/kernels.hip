@@ -389,7 +389,15 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   const bool yin = j >= M && j < nr - M;
   const int yrow = (j < M) ? j : nr - 1 - j;
   const int ytab = (j < M) ? 0 : 2 * TABN;
-  const int ncol = A.ncol;
+  // closure rows along r (LDS reads): unrolled in single precision; in
+  // double precision the registers are not there.  The s closure rows
+  // (memory gathers over NC planes) take one column at a time: issuing
+  // every column's loads together measured slower.
+  constexpr int RU = sizeof(T) == 4 ? NC : 1;
+  // the q = 0 face penalty in this kernel (single precision): blocks of the
+  // first tile column, lane 0 of each row
+  constexpr bool Q0S = q0_in_stage<T>();
+  const bool q0pen = Q0S && A.sat != 0 && x0 == 0;
 
   // prefetch registers: everything plane a needs from memory (own sigma, M,
   // material, Runge-Kutta register; the y-halo and x-halo points of the
@@ -488,6 +496,16 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
     const unsigned o = pa + col;
     if constexpr (!HALO_AHEAD) load_halo(a);
     if constexpr (!LATE_AHEAD) load_late(a);
+    // coefficients of the q = 0 face at the wave's row (one address per
+    // wave), loaded when the plane starts and used by the stage update
+    T fcq[Q0S ? kNumFaceCoef : 1];
+    if constexpr (Q0S) {
+      if (q0pen) {
+        const std::size_t fo = A.face_off[0] + (std::size_t)a * nr + (std::size_t)min(j, nr - 1);
+#pragma unroll
+        for (int kk = 0; kk < kNumFaceCoef; ++kk) fcq[kk] = A.face[fo + (std::size_t)kk * A.face_n[0]];
+      }
+    }
     // ---------------- phase 1: stage plane a in LDS from the prefetched registers
     T sg[6], mq[3], mr[3], ms[3], dqo[9];
     if constexpr (SR) {
@@ -616,7 +634,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
         const bool left = j < M;
         const int rowv = H - y0 + (left ? 0 : nr - 1);
         const int stepr = left ? 1 : -1;
-        for (int cc = 0; cc < ncol; ++cc) {
+#pragma unroll RU
+        for (int cc = 0; cc < NC; ++cc) {
           const T cp = ltab[ytab + yrow * kMaxCols + cc];
           const T cm = ltab[ytab + TABN + yrow * kMaxCols + cc];
           const int rw = rowv + stepr * cc;
@@ -654,7 +673,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
         const int row = left ? a : ns - 1 - a;
         const int zt = left ? 0 : 2 * TABN;
         T sp[3] = {T(0), T(0), T(0)}, sm[3] = {T(0), T(0), T(0)};
-        for (int cc = 0; cc < ncol; ++cc) {
+#pragma unroll 1
+        for (int cc = 0; cc < NC; ++cc) {
           const int k = left ? cc : ns - 1 - cc;
           const unsigned ok = (unsigned)k * plane + col;
           T f[3];
@@ -686,8 +706,11 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
 
       const T v[3] = {vq[0][R], vq[1][R], vq[2][R]};
 
-      // the boundary penalties of face nodes are added by penalty_kernel
-      // after the launch
+      // the penalty of the q = 0 face at its nodes (single precision); the
+      // other boundary penalties are added by penalty_kernel after the launch
+      if constexpr (Q0S) {
+        if (q0pen && tx == 0) face_penalty(fcq, A.gamma[0], T(-1), A.traction[0] != 0, v, sg, rate);
+      }
 
       // Runge-Kutta stage update
       const T dt = A.dt, Ak = A.Ak, Bk = A.Bk;
@@ -1137,23 +1160,27 @@ __global__ __launch_bounds__(512, SBP_STAGE_MIN_WAVES) void stage_kernel_worklis
 template <typename T>
 __device__ __forceinline__ void penalty_body(const StageArgs<T>& A, long long e) {
   const int nq = A.nq, nr = A.nr, ns = A.ns;
-  const long long nA = 2LL * nr * ns, nB = 2LL * (nq - 2) * ns, nC = 2LL * (nq - 2) * (nr - 2);
+  constexpr bool Q0S = q0_in_stage<T>();
+  // q faces (both, or only q = nq-1), r faces (i in [i0, nq-1-i0)), s faces
+  // (the same i, 0 < j < nr-1)
+  const int i0 = Q0S ? 0 : 1, ni = nq - 1 - i0;
+  const long long nA = (Q0S ? 1LL : 2LL) * nr * ns, nB = 2LL * ni * ns, nC = 2LL * ni * (nr - 2);
   int i, j, k;
   if (e < nA) {
     const long long per = (long long)nr * ns, r = e % per;
-    i = e < per ? 0 : nq - 1;
+    i = (Q0S || e >= per) ? nq - 1 : 0;
     j = (int)(r % nr);
     k = (int)(r / nr);
   } else if ((e -= nA) < nB) {
-    const long long per = (long long)(nq - 2) * ns, r = e % per;
+    const long long per = (long long)ni * ns, r = e % per;
     j = e < per ? 0 : nr - 1;
-    i = 1 + (int)(r % (nq - 2));
-    k = (int)(r / (nq - 2));
+    i = i0 + (int)(r % ni);
+    k = (int)(r / ni);
   } else if ((e -= nB) < nC) {
-    const long long per = (long long)(nq - 2) * (nr - 2), r = e % per;
+    const long long per = (long long)ni * (nr - 2), r = e % per;
     k = e < per ? 0 : ns - 1;
-    i = 1 + (int)(r % (nq - 2));
-    j = 1 + (int)(r / (nq - 2));
+    i = i0 + (int)(r % ni);
+    j = 1 + (int)(r / ni);
   } else {
     return;
   }
@@ -1172,7 +1199,9 @@ __device__ __forceinline__ void penalty_body(const StageArgs<T>& A, long long e)
     for (int kk = 0; kk < kNumFaceCoef; ++kk) fc[kk] = A.face[A.face_off[f] + idx + (std::size_t)kk * A.face_n[f]];
     face_penalty(fc, A.gamma[f], eps, A.traction[f], v, sg, rate);
   };
-  if (i == 0) face(0, (std::size_t)k * nr + j, T(-1));
+  // (with the q = 0 face in the stage kernel: only at the nodes of the edge
+  // row, which the stage tiles do not compute)
+  if (i == 0 && (!Q0S || (A.ey && j == nr - 1))) face(0, (std::size_t)k * nr + j, T(-1));
   if (i == nq - 1) face(1, (std::size_t)k * nr + j, T(1));
   if (j == 0) face(2, (std::size_t)k * nq + i, T(-1));
   if (j == nr - 1) face(3, (std::size_t)k * nq + i, T(1));
@@ -1548,7 +1577,7 @@ bool worklist_order_ok(int order) {
 
 template <typename T>
 hipError_t launch_penalty(const StageArgs<T>& a, hipStream_t st) {
-  const long long n = surface_nodes(a.nq, a.nr, a.ns);
+  const long long n = surface_nodes(a.nq, a.nr, a.ns, q0_in_stage<T>());
   hipLaunchKernelGGL(penalty_kernel<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a);
   return hipGetLastError();
 }

@@ -174,8 +174,21 @@ hipError_t launch_penalty(const StageArgs<T>& a, hipStream_t st);
 // surface node counts (surface_nodes)
 template <typename T>
 hipError_t launch_penalty_batch(const BatchArgs<T>& b, hipStream_t st);
-// nodes of the block's surface (each once)
-__host__ __device__ inline long long surface_nodes(int nq, int nr, int ns) {
+// Single precision adds the penalty of the q = 0 face inside the stage
+// kernel, at the nodes its tiles compute (lanes i = 0 of the first tiles
+// along q hold the node's values there, while a separate pass would fetch a
+// whole line of every field per node); double precision, short of
+// registers, leaves it to the penalty kernel.
+template <typename T>
+constexpr bool q0_in_stage() {
+  return sizeof(T) == 4;
+}
+// nodes the penalty kernel visits (each once): the whole surface, or, with
+// the q = 0 face in the stage kernel, the surface without the inside of that
+// face (the q = nq-1 face, the r faces for i < nq-1, the s faces for i <
+// nq-1 and 0 < j < nr-1)
+__host__ __device__ inline long long surface_nodes(int nq, int nr, int ns, bool q0_stage) {
+  if (q0_stage) return 1LL * nr * ns + 2LL * (nq - 1) * ns + 2LL * (nq - 1) * (nr - 2);
   return 2LL * nr * ns + 2LL * (nq - 2) * ns + 2LL * (nq - 2) * (nr - 2);
 }
 template <typename T>
