@@ -391,11 +391,12 @@ int sbp_autotune(sbp_handle h, int reps, int* ty, int* zchunk, double* ms);
 
 /*
  * Fill the handle's scratch buffers -- the state buffer that does not hold
- * the current state (the next stage's output) and the Runge-Kutta register
- * -- with `value` (for instance a NaN), asynchronously.  A check of the
- * ping-pong design: every stage writes every node of its output before the
- * next stage reads it, and the first stage does not read the register, so
- * sbp_step and sbp_rhs results do not depend on these contents.
+ * the current state (the next stage's output), the Runge-Kutta register and
+ * the stage kernel's s closure terms -- with `value` (for instance a NaN),
+ * asynchronously.  A check of the ping-pong design: every stage writes every
+ * node of its output before the next stage reads it, the first stage does
+ * not read the register, and every stage forms the closure terms it reads,
+ * so sbp_step and sbp_rhs results do not depend on these contents.
  */
 int sbp_fill_scratch(sbp_handle h, double value);
 

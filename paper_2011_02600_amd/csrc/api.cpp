@@ -90,7 +90,8 @@ struct sbp_ctx {
   std::size_t ws_bytes = 0;
   // byte offsets in the workspace
   std::size_t off_qa = 0, off_qb = 0, off_dq = 0, off_coef = 0, off_face[6] = {}, off_src = 0,
-              off_rec = 0, off_part = 0, off_bounds = 0, off_tab = 0, off_batch = 0, total = 0;
+              off_rec = 0, off_part = 0, off_bounds = 0, off_tab = 0, off_scl = 0, off_batch = 0,
+              total = 0;
   std::size_t face_n[6] = {};
   int px = 0;
   std::size_t plane = 0, field = 0;
@@ -254,6 +255,7 @@ void layout(sbp_ctx* h) {
   h->off_part = take(kMaxPart * sizeof(double));
   h->off_bounds = take((std::size_t)(g.nq + g.nr + g.ns + 16) * sizeof(int));
   h->off_tab = take((std::size_t)kClosureTab * kMaxM * kMaxCols * es);
+  h->off_scl = take((std::size_t)2 * kMaxM * 6 * h->plane * es);
   h->off_batch = take(batch_region_bytes());
   h->tab_part_bytes = align256((std::size_t)kTabSteps * 5 * kMaxSources * es);
   h->off_clock = take(sizeof(StepClock));
@@ -522,6 +524,7 @@ StageArgs<T> stage_args(sbp_ctx* h) {
   a.inv_h[1] = (T)(g.nr - 1);
   a.inv_h[2] = (T)(g.ns - 1);
   a.tab = (const T*)(h->ws + h->off_tab);
+  a.scl = (T*)(h->ws + h->off_scl);
   return a;
 }
 
@@ -2057,12 +2060,16 @@ int sbp_fill_scratch(sbp_handle h, double value) {
   if (!h) return fail(SBP_EINVAL, "NULL handle");
   char* other = h->ws + (h->cur ? h->off_qa : h->off_qb);
   char* dq = h->ws + h->off_dq;
+  char* scl = h->ws + h->off_scl;
+  const std::size_t nscl = (std::size_t)2 * kMaxM * 6 * h->plane;
   if (h->dtype == SBP_F32) {
     HIPCHK(launch_fill<float>((float*)other, 9 * h->field, (float)value, h->stream));
     HIPCHK(launch_fill<float>((float*)dq, 9 * h->field, (float)value, h->stream));
+    HIPCHK(launch_fill<float>((float*)scl, nscl, (float)value, h->stream));
   } else {
     HIPCHK(launch_fill<double>((double*)other, 9 * h->field, value, h->stream));
     HIPCHK(launch_fill<double>((double*)dq, 9 * h->field, value, h->stream));
+    HIPCHK(launch_fill<double>((double*)scl, nscl, value, h->stream));
   }
   return SBP_OK;
 }

@@ -330,6 +330,62 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   // ring slot of plane k (k >= -Q)
   auto slot = [&](int k) { return (k + 7 * QD) % QD; };
 
+  __syncthreads();  // closure and weight rows written, windows zeroed
+
+  // s closure rows.  The terms h D+_s v and h D-_s F_s of a closure plane
+  // gather its row's NC planes; gathered plane by plane, the M closure planes
+  // would read those planes M times.  The block forms the terms of all
+  // closure rows of its planes here, in one pass over the NC planes, keeps
+  // them in the workspace (A.scl) and reads them back at the plane.
+  {
+    const unsigned cl = act ? col : 0u;
+    constexpr int PU = sizeof(T) == 4 ? NC : 5;
+#pragma unroll 1
+    for (int side = 0; side < 2; ++side) {
+      // planes with a closure row on this side (left rows take precedence)
+      const int lo = side == 0 ? z0 : max(z0, max(ns - M, M));
+      const int hi = side == 0 ? min(z1, M) : z1;
+      if (lo >= hi) continue;
+      const int zt = side == 0 ? 0 : 2 * TABN;
+      // pass 0: h D+_s v from v; pass 1: h D-_s F_s from sigma and M_s
+#pragma unroll 1
+      for (int pass = 0; pass < 2; ++pass) {
+        T acc[M][3];
+#pragma unroll
+        for (int r = 0; r < M; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) acc[r][c] = T(0);
+#pragma unroll PU
+        for (int cc = 0; cc < NC; ++cc) {
+          const int k = side == 0 ? cc : ns - 1 - cc;
+          const unsigned ok = (unsigned)k * plane + cl;
+          T x[3];
+          if (pass == 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) x[c] = gq.ld(c, ok);
+          } else {
+            sflux(ok, x);
+          }
+#pragma unroll
+          for (int r = 0; r < M; ++r) {
+            const T w = ltab[zt + pass * TABN + r * kMaxCols + cc];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[r][c] += w * x[c];
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < M; ++r) {
+          const int ar = side == 0 ? r : ns - 1 - r;
+          if (act && ar >= lo && ar < hi) {
+            T* dst = A.scl + (std::size_t)((side * kMaxM + r) * 6 + 3 * pass) * plane + col;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dst[(std::size_t)c * plane] = acc[r][c];
+          }
+        }
+      }
+    }
+  }
+
   // register queue vq[s] = v(a - R + s); ring holds F_s(a - Q .. a + R)
   T vq[3][QD];
 #pragma unroll
@@ -376,7 +432,6 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   // FP32 keeps the lane's weights in registers; FP64 reads them from LDS
   constexpr bool QWREG = sizeof(T) == 4;
   T wqp[QWREG ? NC : 1], wqm[QWREG ? NC : 1];
-  __syncthreads();  // weight rows written, windows zeroed
   if constexpr (QWREG) {
 #pragma unroll
     for (int t = 0; t < NC; ++t) {
@@ -496,6 +551,22 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
     const unsigned o = pa + col;
     if constexpr (!HALO_AHEAD) load_halo(a);
     if constexpr (!LATE_AHEAD) load_late(a);
+    // s closure terms of a closure plane: loaded when the plane starts in
+    // single precision, where they are used in double precision
+    constexpr bool SCL_EARLY = sizeof(T) == 4;
+    const bool sclose = !(a >= M && a < ns - M);
+    auto scl_at = [&](unsigned c) -> const T* {
+      const int side = a < M ? 0 : 1, r = side == 0 ? a : ns - 1 - a;
+      return A.scl + (std::size_t)((side * kMaxM + r) * 6 + c) * plane;
+    };
+    T pscl[SCL_EARLY ? 6 : 1];
+    if constexpr (SCL_EARLY) {
+      if (sclose) {
+        const unsigned cl = act ? col : 0u;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) pscl[c] = scl_at(c)[cl];
+      }
+    }
     // coefficients of the q = 0 face at the wave's row (one address per
     // wave), loaded when the plane starts and used by the stage update
     T fcq[Q0S ? kNumFaceCoef : 1];
@@ -652,7 +723,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
         }
       }
       // s direction
-      if (__builtin_expect(a >= M && a < ns - M, 1)) {
+      if (__builtin_expect(!sclose, 1)) {
         const int s0 = slot(a - Q);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -669,28 +740,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
           sched_fence<T>();
         }
       } else {
-        const bool left = a < M;
-        const int row = left ? a : ns - 1 - a;
-        const int zt = left ? 0 : 2 * TABN;
-        T sp[3] = {T(0), T(0), T(0)}, sm[3] = {T(0), T(0), T(0)};
-#pragma unroll 1
-        for (int cc = 0; cc < NC; ++cc) {
-          const int k = left ? cc : ns - 1 - cc;
-          const unsigned ok = (unsigned)k * plane + col;
-          T f[3];
-          sflux(ok, f);
-          const T cp = ltab[zt + row * kMaxCols + cc];
-          const T cm = ltab[zt + TABN + row * kMaxCols + cc];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            sp[c] += cp * gq.ld(c, ok);
-            sm[c] += cm * f[c];
-          }
-        }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          u[2][c] = sp[c] * ihs;
-          dv[c] += sm[c] * ihs;
+          u[2][c] = (SCL_EARLY ? pscl[SCL_EARLY ? c : 0] : scl_at(c)[col]) * ihs;
+          dv[c] += (SCL_EARLY ? pscl[SCL_EARLY ? 3 + c : 0] : scl_at(3 + c)[col]) * ihs;
         }
       }
 

@@ -17,6 +17,10 @@ struct StageArgs {
   const T* coef;      // 12 fields: M[xi][c] (3 xi + c), lambda/J, mu/J, 1/(rho J)
   const T* face;      // workspace base for the face coefficient arrays
   const int* bounds;  // tile bounds: q (nxt+1), r (nyt+1), s (nzc+1)
+  // s closure terms of the closure planes, written and read by the stage
+  // kernel: value (side, row, c) of node col at ((side * kMaxM + row) * 6 +
+  // c) * plane + col; c = 0..2: h D+_s v_c, 3..5: h D-_s F_s,c
+  T* scl;
   NodeMap nm;         // node -> element offset in a field
   std::size_t face_off[6];
   std::size_t face_n[6];
