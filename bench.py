@@ -74,9 +74,11 @@ def kernel_sha():
     return h.hexdigest()[:16]
 
 
-def read_traffic():
-    """HBM bytes per stage launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source (else None)."""
+def read_traffic(key="hbm_bytes_per_launch"):
+    """HBM bytes per stage launch (`key`: hbm_bytes_per_launch for the
+    single-precision kernel, hbm_bytes_per_launch_f64 for the double-precision
+    one) from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source (else None)."""
     if not os.path.exists(PROFILE):
         return None
     vals = {}
@@ -88,7 +90,7 @@ def read_traffic():
     if vals.get("kernel_source_sha256_16") != kernel_sha():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
 
@@ -539,8 +541,12 @@ def main():
     if not args.no_fp64 and args.dtype == "f32":
         # the same workload in the paper's arithmetic (double precision)
         m64 = measure_topo(args, wl, "f64", order, sbp, torch, np, dev)
+        t64 = read_traffic("hbm_bytes_per_launch_f64") if order == 6 else None
+        r64 = dict(m64["roofline"], traffic=None if t64 is None else int(t64),
+                   traffic_rate_gbs=None if t64 is None
+                   else round(t64 / (m64["roofline"]["avg_launch_ms"] / 1e3) / 1e9, 1))
         out["fp64"] = {"value": m64["value"], "unit": "Mpts*stage/s", "ms_per_step": m64["ms_per_step"],
-                       "steps": args.steps, "roofline": m64["roofline"]}
+                       "steps": args.steps, "roofline": r64}
     if not args.no_cpu:
         print("bench: cpu oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, order)
