@@ -96,9 +96,9 @@ int sbp_workspace_bytes(int nq, int nr, int ns, int order, int dtype, size_t* by
  *               precision (x_xi = D0 x with D0 = (D+ + D-)/2, J = det, and the
  *               conservative cofactor form of J dxi/dx); a non-positive
  *               Jacobian anywhere is SBP_EINVAL.
- *  order        interior order of accuracy of the upwind pair, 2 to 7
- *               (Table tab:upwind; 7 with SBP_F32 only, whose tiles fit
- *               the LDS; 8 and 9 are SBP_EINVAL).  The boundary closures are accurate to
+ *  order        interior order of accuracy of the upwind pair, 2 to 8
+ *               (Table tab:upwind; 7 and 8 with SBP_F32 only, whose tiles
+ *               fit the LDS; 9 is SBP_EINVAL).  The boundary closures are accurate to
  *               order order / 2 (rounded down); the paper does not print
  *               them: the library constructs them from the SBP and upwind
  *               properties of Sec. 4.1, the entries those leave free fixed
@@ -346,7 +346,8 @@ int sbp_energy(sbp_handle h, double* E);
 
 /*
  * Launch shape of the stage kernel: ty rows of 64 points per thread block
- * (8 or 16) and zchunk planes per block along s (>= 1; 0 = automatic).
+ * (8 or 16; 16 only for SBP_F32 at orders 2 to 7, else SBP_EINVAL) and
+ * zchunk planes per block along s (>= 1; 0 = automatic).
  * Does not change results beyond floating-point summation order (it does
  * not change it at all: every node is computed by the same instructions).
  */
@@ -381,7 +382,7 @@ int sbp_profile(sbp_handle h, double* stage_ms, double* edge_ms, long long* nsta
 /*
  * Launch-shape autotuner.  Times `reps` right-hand-side evaluations of the
  * handle's own grid for each candidate launch shape (tile height 8, and 16
- * for SBP_F32 at orders up to 6; the cost model's number of s-chunks and one
+ * for SBP_F32 at orders up to 7; the cost model's number of s-chunks and one
  * fewer / one more) and keeps the fastest, as sbp_set_launch would.  Writes
  * the chosen tile height, s-chunk length and its time per evaluation (ms) to
  * the outputs (each may be NULL).  The state and time are not changed; call

@@ -168,11 +168,11 @@ std::size_t field_elems(int nq, int nr, int ns, std::size_t es) {
 }
 
 int check_dims(int nq, int nr, int ns, int order, int dtype) {
-  if (order == 8 || order == 9)
-    return fail(SBP_EINVAL, "order %d is not supported: its 5-point halo does not fit the 8-row stage tiles", order);
-  if (order < 2 || order > 7) return fail(SBP_EINVAL, "order must be 2 to 7 (got %d)", order);
-  if (order == 7 && dtype == SBP_F64)
-    return fail(SBP_EINVAL, "order 7 runs in SBP_F32 only: its double-precision stage tiles exceed the LDS");
+  if (order == 9)
+    return fail(SBP_EINVAL, "order 9 is not supported: no boundary closure is constructed for it");
+  if (order < 2 || order > 8) return fail(SBP_EINVAL, "order must be 2 to 8 (got %d)", order);
+  if (order >= 7 && dtype == SBP_F64)
+    return fail(SBP_EINVAL, "order %d runs in SBP_F32 only: its double-precision stage tiles exceed the LDS", order);
   if (dtype != SBP_F32 && dtype != SBP_F64) return fail(SBP_EINVAL, "dtype must be SBP_F32 or SBP_F64");
   const int mn = 2 * order;
   if (nq < mn || nr < mn || ns < mn)
@@ -1295,7 +1295,7 @@ namespace {
 template <typename T>
 int do_autotune(sbp_ctx* h, int reps, int* best_ty, int* best_zchunk, double* best_ms) {
   std::vector<int> tys{8};
-  if (sizeof(T) == 4) tys.push_back(16);
+  if (sizeof(T) == 4 && h->order <= 7) tys.push_back(16);  // 16-row order-8 tiles exceed the LDS
   const std::vector<Src> saved = h->src;
   h->src.clear();
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -2033,6 +2033,8 @@ int sbp_set_launch(sbp_handle h, int ty, int zchunk) {
   if (!h) return fail(SBP_EINVAL, "NULL handle");
   if (ty != 8 && ty != 16) return fail(SBP_EINVAL, "ty must be 8 or 16");
   if (ty < h->cl.m) return fail(SBP_EINVAL, "ty must be >= %d for order %d", h->cl.m, h->order);
+  if (ty == 16 && (h->dtype == SBP_F64 || h->order == 8))
+    return fail(SBP_EINVAL, "16-row tiles exist for SBP_F32 orders 2 to 7 only (their LDS)");
   if (zchunk < 0) return fail(SBP_EINVAL, "zchunk must be >= 0");
   h->ty = ty;
   h->zchunk = zchunk;

@@ -16,7 +16,10 @@
 // than the interior stencil's) with positive weights, at the simplest
 // rational of equal radius: order 3 A[1][2] = 1/2, order 5 A[2][4] = 1/4 and
 // A[3][4] = 1/2, order 6 A[4][5] = 101/125, order 7 A[5][6] = 2/3,
-// A[4][6] = A[3][6] = 0, A[4][5] = 3/5.  For interior order 2p + 1 the
+// A[4][6] = A[3][6] = 0, A[4][5] = 3/5, order 8 A[6][7] = 5/6, A[5][7] = -1/5,
+// A[5][6] = 3/4 (spectral radius 2.35 against the interior 2.10 at N = 80;
+// the radius depends sharply on these entries and its minimum lies at
+// irrational values).  For interior order 2p + 1 the
 // boundary accuracy is p, as for 2p.  The system is solved with Householder
 // QR in long double.
 #include <cmath>
@@ -34,7 +37,9 @@ struct Row {
   int n;
 };
 
-// Table tab:upwind, orders 2 to 7: alpha_{-r} .. alpha_{q}.
+// Table tab:upwind, orders 2 to 8: alpha_{-r} .. alpha_{q}.  Order 8's
+// alpha_4 is printed +1/28; -1/28 makes the coefficients sum to zero (a
+// consistent difference) and the stencil eighth-order accurate.
 const Row kTable[] = {
     {2, 0, {-3, 2, -1}, {2, 1, 2}, 3},
     {3, 1, {-1, -1, 1, -1}, {3, 2, 1, 6}, 4},
@@ -42,6 +47,7 @@ const Row kTable[] = {
     {5, 2, {1, -1, -1, 1, -1, 1}, {20, 2, 3, 1, 4, 30}, 6},
     {6, 2, {1, -2, -7, 4, -1, 2, -1}, {30, 5, 12, 3, 2, 15, 60}, 7},
     {7, 3, {-1, 1, -3, -1, 1, -3, 1, -1}, {105, 10, 5, 4, 1, 10, 15, 140}, 8},
+    {8, 3, {-1, 1, -1, -9, 5, -1, 1, -1, 1}, {168, 14, 2, 20, 4, 2, 6, 28, 280}, 9},
 };
 
 // Corner-block entries A[i][j] = num/den left free by the accuracy conditions.
@@ -57,6 +63,9 @@ const FreeEntry kFree[] = {
     {7, 4, 6, 0, 1},
     {7, 3, 6, 0, 1},
     {7, 4, 5, 3, 5},
+    {8, 6, 7, 5, 6},
+    {8, 5, 7, -1, 5},
+    {8, 5, 6, 3, 4},
 };
 
 long double binom(int n, int k) {
@@ -109,7 +118,7 @@ bool build_closure(int order, Closure* out, const char** err) {
   for (const Row& t : kTable)
     if (t.order == order) row = &t;
   if (!row) {
-    *err = "unsupported order (2 to 7)";
+    *err = "unsupported order (2 to 8)";
     return false;
   }
   const int r = row->r;

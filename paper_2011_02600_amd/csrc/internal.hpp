@@ -6,11 +6,11 @@
 
 namespace sbp {
 
-// Largest closure block (interior order 7: 7 rows x 11 columns).
-constexpr int kMaxM = 7;
-constexpr int kMaxCols = 11;
+// Largest closure block (interior order 8: 8 rows x 13 columns).
+constexpr int kMaxM = 8;
+constexpr int kMaxCols = 13;
 constexpr int kMaxSources = 4;
-constexpr int kMaxSrcWidth = 8;   // 2 (p + 1) for p = 3
+constexpr int kMaxSrcWidth = 10;  // 2 (p + 1) for p = 4
 constexpr int kNumFaceCoef = 10;  // per face node, see FaceCoef
 constexpr int kNumCoef = 12;      // per node: M[3][3], lambda/J, mu/J, 1/(rho J)
 

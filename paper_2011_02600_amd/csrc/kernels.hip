@@ -66,6 +66,13 @@ struct Stencil<7> {
   static constexpr int R = 3, Q = 4, M = 7;
   static constexpr double a[8] = {-1.0 / 105, 1.0 / 10, -3.0 / 5, -1.0 / 4, 1.0, -3.0 / 10, 1.0 / 15, -1.0 / 140};
 };
+// (alpha_4 printed +1/28; -1/28 sums the coefficients to zero)
+template <>
+struct Stencil<8> {
+  static constexpr int R = 3, Q = 5, M = 8;
+  static constexpr double a[9] = {-1.0 / 168, 1.0 / 14, -1.0 / 2,  -9.0 / 20,  5.0 / 4,
+                                  -1.0 / 2,   1.0 / 6,  -1.0 / 28, 1.0 / 280};
+};
 
 // ---------------------------------------------------------------------------
 // element `off` of the field starting at the uniform address `base`: the byte
@@ -222,6 +229,12 @@ struct StageLds {
   static constexpr std::size_t bytes = total * sizeof(T);
 };
 
+// whether stage_body<T, ORDER, TY> is built: its LDS fits
+template <typename T, int ORDER, int TY>
+constexpr bool stage_built() {
+  return StageLds<T, ORDER, TY>::bytes <= kLdsBytes;
+}
+
 template <typename T, int ORDER, int TY, bool BUF>
 __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile, char* lds) {
   using S = Stencil<ORDER>;
@@ -236,7 +249,11 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   constexpr int NYH = 2 * H * 64; // y-halo points
   constexpr int NXH = 2 * H * TY; // x-halo points
   constexpr int TABN = L::TABN;
-  static_assert(NYH <= NT, "one y-halo point per thread");
+  // one y-halo point per thread; halo rows beyond the first NT / 64 (order
+  // 8: 10 rows for 8-row tiles) are upper rows past the flux's reach r,
+  // which need v only and take a second point in the first threads
+  constexpr int NYH2 = NYH > NT ? NYH - NT : 0;
+  static_assert(NYH2 <= NT && (NYH2 == 0 || NT / 64 >= H + R), "y halo");
   static_assert(TY >= M, "r closure rows must fit in one tile");
   static_assert(L::bytes <= kLdsBytes, "stage tile exceeds the LDS");
   T* const lv = reinterpret_cast<T*>(lds) + L::o_lv;
@@ -288,8 +305,13 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
     }
     tq[e] = w;
   }
+  // Window positions that no load fills are read with zero weights (the
+  // padded q taps; closure rows along r that end before the row range does,
+  // as order 8's flux rows beyond r above the first tile): they must hold
+  // finite values, whatever an earlier kernel left in this LDS
   for (int e = threadIdx.y * 64 + threadIdx.x; e < 3 * VX * VY; e += NT) lv[e] = T(0);
   for (int e = threadIdx.y * 64 + threadIdx.x; e < 3 * QX * TY; e += NT) lq[e] = T(0);
+  for (int e = threadIdx.y * 64 + threadIdx.x; e < 3 * RX * VY; e += NT) lr[e] = T(0);
 
   // y halo: rows y0-H..y0-1 and y0+TY..y0+TY+H-1, columns x0..x1-1
   const int yh_r = tid >> 6;
@@ -306,6 +328,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   // (with an edge row after the last tile, the boundary closure rows of that
   // tile also read the flux of the edge row, which may lie beyond R)
   const bool yh_f = yh_in && (yh_r < H + R || y1 == nr - 1);
+  // the second point: halo row NT / 64 + (tid >> 6), an upper row
+  const int yh2_r = NT / 64 + (tid >> 6);
+  const int yh2_gy = y0 + TY + yh2_r - H;
+  const bool yh2_v = NYH2 > 0 && tid < NYH2 && yh_gx < x1 && yh2_gy < nr;
+  const int yh2_ly = TY + yh2_r;
+  const unsigned yh2_col = yh2_v ? (unsigned)yh2_gy * px + (unsigned)yh_gx : 0u;
   // x halo: columns x0-H..x0-1 and x1..x1+H-1, rows y0..y0+TY-1.  Column
   // nq-1 (the right halo of the last tile) is read from the last-column
   // array of the fields.
@@ -459,7 +487,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   // thread), loaded one plane ahead so that the loads of plane a+1 overlap
   // the arithmetic of plane a
   constexpr int NSG = SR ? 1 : 6, NMS = SR ? 6 : 9;
-  T p_sg[NSG], p_m[NMS], p_mat[3], p_dq[9], p_hy[12], p_hx[12];
+  T p_sg[NSG], p_m[NMS], p_mat[3], p_dq[9], p_hy[12], p_hx[12], p_hy2[NYH2 > 0 ? 3 : 1];
   const bool rdq = A.read_dq != 0;
   // the halo points of a plane are loaded with the plane's other data one
   // plane ahead; in double precision their registers do not fit beside the
@@ -480,6 +508,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
     for (int c = 3; c < 9; ++c) p_hy[c] = gq.ld(c, ohf);
 #pragma unroll
     for (int c = 0; c < 3; ++c) p_hy[9 + c] = gc.ld(3 + c, ohf);
+    if constexpr (NYH2 > 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) p_hy2[c] = gq.ld(c, pa + yh2_col);
+    }
     if (xh_wave) {
       const unsigned ox = xh_edge ? (unsigned)(A.nm.cbase + (long long)a * nr + xh_gy) : pa + xh_col;
 #pragma unroll
@@ -621,6 +653,14 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
       lv[0 * VX * VY + wv] = h[0];
       lv[1 * VX * VY + wv] = h[1];
       lv[2 * VX * VY + wv] = h[2];
+    }
+    if constexpr (NYH2 > 0) {
+      if (yh2_v) {  // v of the second y-halo point
+        const int wv = yh2_ly * VX + (tid & 63) + H;
+        lv[0 * VX * VY + wv] = p_hy2[0];
+        lv[1 * VX * VY + wv] = p_hy2[1];
+        lv[2 * VX * VY + wv] = p_hy2[2];
+      }
     }
     if (yh_f) {  // r-flux of the y-halo point
       const T* h = p_hy;
@@ -1399,11 +1439,11 @@ __global__ void energy_kernel(EnergyArgs<T> E) {
 }
 
 // ---------------------------------------------------------------------------
-// launchers
-// 16-row tiles, and order 7 (its s-flux ring), exceed the LDS in double
+// launchers (a stage body whose LDS does not fit is not built: 16-row tiles
+// and orders 7 and 8 in double, order 8 with 16-row tiles)
 template <typename T, int ORDER, int TY>
 static hipError_t launch_stage_t(const StageArgs<T>& a, hipStream_t st) {
-  if constexpr (sizeof(T) == 8 && (TY == 16 || ORDER == 7)) {
+  if constexpr (!stage_built<T, ORDER, TY>()) {
     return hipErrorInvalidValue;
   } else {
     const int nb = ((a.ntiles + 7) / 8) * 8;
@@ -1426,6 +1466,7 @@ hipError_t launch_stage(int order, int ty, const StageArgs<T>& a, hipStream_t st
     if (order == 5) return launch_stage_t<T, 5, 16>(a, st);
     if (order == 6) return launch_stage_t<T, 6, 16>(a, st);
     if (order == 7) return launch_stage_t<T, 7, 16>(a, st);
+    if (order == 8) return launch_stage_t<T, 8, 16>(a, st);
   } else {
     if (order == 2) return launch_stage_t<T, 2, 8>(a, st);
     if (order == 3) return launch_stage_t<T, 3, 8>(a, st);
@@ -1433,6 +1474,7 @@ hipError_t launch_stage(int order, int ty, const StageArgs<T>& a, hipStream_t st
     if (order == 5) return launch_stage_t<T, 5, 8>(a, st);
     if (order == 6) return launch_stage_t<T, 6, 8>(a, st);
     if (order == 7) return launch_stage_t<T, 7, 8>(a, st);
+    if (order == 8) return launch_stage_t<T, 8, 8>(a, st);
   }
   return hipErrorInvalidValue;
 }
@@ -1442,7 +1484,7 @@ hipError_t launch_stage(int order, int ty, const StageArgs<T>& a, hipStream_t st
 // addressings, edge, penalty, source and receiver kernels)
 template <typename T, int ORDER, int TY>
 static std::size_t step_scratch_t() {
-  if constexpr (sizeof(T) == 8 && (TY == 16 || ORDER == 7)) {
+  if constexpr (!stage_built<T, ORDER, TY>()) {
     return 0;
   } else {
     std::size_t m = 0;
@@ -1470,6 +1512,7 @@ std::size_t step_scratch(int order, int ty) {
     if (order == 5) return step_scratch_t<T, 5, 16>();
     if (order == 6) return step_scratch_t<T, 6, 16>();
     if (order == 7) return step_scratch_t<T, 7, 16>();
+    if (order == 8) return step_scratch_t<T, 8, 16>();
   } else {
     if (order == 2) return step_scratch_t<T, 2, 8>();
     if (order == 3) return step_scratch_t<T, 3, 8>();
@@ -1477,6 +1520,7 @@ std::size_t step_scratch(int order, int ty) {
     if (order == 5) return step_scratch_t<T, 5, 8>();
     if (order == 6) return step_scratch_t<T, 6, 8>();
     if (order == 7) return step_scratch_t<T, 7, 8>();
+    if (order == 8) return step_scratch_t<T, 8, 8>();
   }
   return (std::size_t)-1;
 }
@@ -1529,6 +1573,8 @@ hipError_t launch_edge(int order, const StageArgs<T>& a, hipStream_t st) {
     hipLaunchKernelGGL((edge_kernel<T, 6, KZ>), dim3(nb), dim3(64, KZ), 0, st, a);
   else if (order == 7)
     hipLaunchKernelGGL((edge_kernel<T, 7, KZ>), dim3(nb), dim3(64, KZ), 0, st, a);
+  else if (order == 8)
+    hipLaunchKernelGGL((edge_kernel<T, 8, KZ>), dim3(nb), dim3(64, KZ), 0, st, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1536,7 +1582,7 @@ hipError_t launch_edge(int order, const StageArgs<T>& a, hipStream_t st) {
 
 template <typename T, int ORDER, int TY>
 static hipError_t launch_stage_batch_t(const BatchArgs<T>& b, bool buf, hipStream_t st) {
-  if constexpr (sizeof(T) == 8 && (TY == 16 || ORDER == 7)) {
+  if constexpr (!stage_built<T, ORDER, TY>()) {
     return hipErrorInvalidValue;
   } else {
     const int nb = ((b.total + 7) / 8) * 8;
@@ -1558,6 +1604,7 @@ hipError_t launch_stage_batch(int order, int ty, const BatchArgs<T>& b, bool buf
     if (order == 5) return launch_stage_batch_t<T, 5, 16>(b, buf, st);
     if (order == 6) return launch_stage_batch_t<T, 6, 16>(b, buf, st);
     if (order == 7) return launch_stage_batch_t<T, 7, 16>(b, buf, st);
+    if (order == 8) return launch_stage_batch_t<T, 8, 16>(b, buf, st);
   } else {
     if (order == 2) return launch_stage_batch_t<T, 2, 8>(b, buf, st);
     if (order == 3) return launch_stage_batch_t<T, 3, 8>(b, buf, st);
@@ -1565,6 +1612,7 @@ hipError_t launch_stage_batch(int order, int ty, const BatchArgs<T>& b, bool buf
     if (order == 5) return launch_stage_batch_t<T, 5, 8>(b, buf, st);
     if (order == 6) return launch_stage_batch_t<T, 6, 8>(b, buf, st);
     if (order == 7) return launch_stage_batch_t<T, 7, 8>(b, buf, st);
+    if (order == 8) return launch_stage_batch_t<T, 8, 8>(b, buf, st);
   }
   return hipErrorInvalidValue;
 }
@@ -1585,6 +1633,8 @@ hipError_t launch_edge_batch(int order, const BatchArgs<T>& b, hipStream_t st) {
     hipLaunchKernelGGL((edge_kernel_batch<T, 6, KZ>), dim3(b.total), dim3(64, KZ), 0, st, b);
   else if (order == 7)
     hipLaunchKernelGGL((edge_kernel_batch<T, 7, KZ>), dim3(b.total), dim3(64, KZ), 0, st, b);
+  else if (order == 8)
+    hipLaunchKernelGGL((edge_kernel_batch<T, 8, KZ>), dim3(b.total), dim3(64, KZ), 0, st, b);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -110,6 +110,12 @@ RHS_CASES = [
     (7, (14, 14, 14), "f32", 0),
     (7, (17, 19, 70), "f32", 1),
     (7, (15, 25, 97), "f32", 0),
+    # interior order 8 (FP32 only): minimum size, ragged multi-tile shapes,
+    # edge-kernel shape
+    (8, (16, 16, 16), "f32", 0),
+    (8, (17, 19, 70), "f32", 1),
+    (8, (18, 25, 97), "f32", 0),
+    (8, (17, 17, 65), "f32", 1),
 ]
 
 
@@ -146,7 +152,8 @@ def test_rhs_parity(order, shape, dtype, variant):
 
 @pytest.mark.parametrize("dtype,order,size", [(d, o, sz) for d in ("f64", "f32")
                                               for o, sz in ((6, (49, 45, 37)), (6, (65, 41, 33)), (3, (65, 41, 33)),
-                                                            (5, (49, 45, 37)))] + [("f32", 7, (65, 41, 33))])
+                                                            (5, (49, 45, 37)))] + [("f32", 7, (65, 41, 33)),
+                                                                                    ("f32", 8, (65, 41, 33))])
 def test_topo_layer_small_100_steps(dtype, order, size):
     """The curvilinear layered workload (topography, transfinite mesh, soft
     layer over a half-space, Ricker moment source, surface receivers) at a
@@ -155,7 +162,8 @@ def test_topo_layer_small_100_steps(dtype, order, size):
     like the full-size workload."""
     nq, nr, ns = size
     say("case: topo_layer %dx%dx%d order %d %s 100 steps" % (nq, nr, ns, order, dtype))
-    wl = W.topo_layer(nq=nq, nr=nr, ns=ns, nrec_side=4)
+    # order 8's closure has the largest spectral radius of the orders: CFL 0.25
+    wl = W.topo_layer(nq=nq, nr=nr, ns=ns, nrec_side=4, cfl=0.25 if order == 8 else 0.5)
     s = make_solver(wl["xyz"], order, dtype, wl["gamma"], medium=(wl["rho"], wl["cp"], wl["cs"]))
     s.add_source(wl["src_xi"], wl["src_M"], 0, wl["src_f0"], wl["src_t0"])
     traces = s.record(wl["receivers"], 100)
@@ -513,3 +521,32 @@ def test_autotune_keeps_state_and_picks_a_candidate():
     got = s.get_state().cpu().numpy().astype(np.float64)
     s.close()
     assert rel_max(got, want) < 1e-5
+
+
+def test_order8_rhs_after_double_precision_kernels():
+    """Window positions that the stage kernel reads with zero weights (order
+    8's flux rows beyond r above the first tile) are cleared when a block
+    starts: a single-precision order-8 right-hand side after double-precision
+    kernels (whose data the LDS still holds, some of it NaN or Inf as
+    single-precision words) equals the oracle's."""
+    say("case: order 8 f32 rhs after f64 kernels")
+    xyz = W.warped_mesh(65, 65, 49, seed=21)
+    med = W.random_medium((49, 65, 65), 22)
+    s64 = make_solver(xyz, 6, "f64", [1, 0, 0.5, 0, -1, 0], medium=med)
+    s64.set_state(W.random_state((49, 65, 65), 23, smooth=True))
+    s64.step(3, 1e-3)
+    s64.close()
+    ns, nr, nq = 17, 18, 19
+    xyz = W.warped_mesh(nq, nr, ns, seed=24)
+    med = W.random_medium((ns, nr, nq), 25)
+    Q = W.random_state((ns, nr, nq), 26, smooth=True)
+    gamma = [0, 0, 0, 0, 0, 1]
+    s = make_solver(xyz, 8, "f32", gamma, medium=med)
+    s.set_state(Q)
+    got = s.rhs(0.0).cpu().numpy().astype(np.float64)
+    s.close()
+    blk = E.Block(xyz, 8).set_material(*med)
+    want = E.rhs(blk, Q, 0.0, gamma, E.SAT_CHARACTERISTIC, [])
+    err = rel_max(got, want)
+    say("  rel max = %.3e" % err)
+    assert np.isfinite(got).all() and err <= 1e-5
