@@ -45,6 +45,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0  # dense BF16 matrix-core peak
 # algorithmic words per node per stage: read Q_in (9) + 13 coefficients (the
 # nine metric terms, J^-1, (rho J)^-1, lambda, mu), read the Runge-Kutta
 # register (9, stages 2-5 only), write it (9) and Q_out (9): 40 words in the
@@ -230,13 +231,13 @@ def run_surrogate(args, W, sbp, torch, np, dev):
     log("surrogate: solving %d shots" % (ntr + nte))
     y, gen_s = SG.solve_batch(sbp, torch, case, fields, dev, log=log)
     d = torch.tensor(np.stack(fields), dtype=torch.float32, device=dev)
-    sur = SG.Surrogate(nn, torch, case, dev)
+    sur = SG.Surrogate(nn, torch, case, dev, members=args.sur_members)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hist = sur.train(d[:ntr - nval], y[:ntr - nval], epochs=args.sur_epochs, log=log)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    val_err, _ = sur.calibrate(d[ntr - nval:ntr], y[ntr - nval:ntr])
+    val_err, val_sc = sur.calibrate(d[ntr - nval:ntr], y[ntr - nval:ntr])
     # held-out media: the solver alone, then the surrogate (timed separately)
     log("surrogate: held-out solver run")
     y_test, solver_s = SG.solve_batch(sbp, torch, case, fields[ntr:], dev, log=log)
@@ -244,13 +245,41 @@ def run_surrogate(args, W, sbp, torch, np, dev):
     sur.predict(dt_[:8])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    pred = sur.predict(dt_)
+    pred, score = sur.predict_with_score(dt_)
     torch.cuda.synchronize()
     infer_s = time.perf_counter() - t0
     err = SG.Surrogate.rel_err(pred, y_test)
     err_mean_trace = SG.Surrogate.rel_err(sur.ymean.expand_as(y_test), y_test)
-    acc = sur.score(dt_) <= sur.tau
+    acc = score <= sur.tau
+    # the rejected media go to the solver (its batched time per shot)
     mixed_s = infer_s + solver_s * float(np.mean(~acc))
+    # other error budgets: threshold from the calibration samples, then the
+    # held-out acceptance and the combined speedup
+    sweep = []
+    for budget in (0.05, 0.10, 0.15, 0.20):
+        tau = SG.Surrogate.threshold(val_err, val_sc, budget)
+        ok = score <= tau
+        sweep.append({"budget_p95": budget, "accepted": int(ok.sum()),
+                      "accepted_rel_l2_p95": float(np.quantile(err[ok], 0.95)) if ok.any() else None,
+                      "speedup": round(solver_s / (infer_s + solver_s * float(np.mean(~ok))), 3)})
+    rank = lambda a: np.argsort(np.argsort(a))
+    spearman = float(np.corrcoef(rank(score), rank(err))[0, 1])
+    # the network's GEMMs over one training step (forward + backward, one
+    # batch of 8 media, first member): flops, algorithmic bytes and time
+    net = sur.nets[0]
+    xb = sur._x(d[:8]).contiguous()
+    net.forward(xb)
+    torch.cuda.synchronize()
+    nn.gemm_profile(True)
+    out8 = net.forward(xb)
+    _, dy8 = net.loss(out8, ((y[:8] - sur.ymean) / sur.yscale).contiguous(), scale=1.0 / 8)
+    net.backward(dy8)
+    torch.cuda.synchronize()
+    gs = nn.gemm_profile_summary(nn.gemm_profile(False))
+    ai = gs["flops"] / gs["bytes"]
+    tflops = gs["flops"] / (gs["ms"] / 1e3) / 1e12
+    gbs = gs["bytes"] / (gs["ms"] / 1e3) / 1e9
+    bound = "hbm" if ai < PEAK_BF16_TFLOPS * 1e3 / PEAK_HBM_GBS else "mfma"
     out = {
         "metric": "speedup over the solver (surrogate with fallback, held-out media, <= 5 %% relative L2 "
                   "trace error on the accepted ones)",
@@ -270,7 +299,8 @@ def run_surrogate(args, W, sbp, torch, np, dev):
                                "source, %d receivers x %d samples of v_z; spectral operator (4 cosine-spectral "
                                "layers, width 32, 8^3 modes)" % (case["n"], case["order"], case["corr_cells"],
                                                                  case["amp"], len(case["receivers"]), case["T"]),
-                   "train": ntr - nval, "calibration": nval, "test": nte, "epochs": args.sur_epochs},
+                   "train": ntr - nval, "calibration": nval, "test": nte, "epochs": args.sur_epochs,
+                   "members": len(sur.nets)},
         "solver_s_per_shot": round(solver_s / nte, 5),
         "surrogate_s_per_shot": round(infer_s / nte, 6),
         "surrogate_only_speedup": round(solver_s / infer_s, 2),
@@ -278,10 +308,25 @@ def run_surrogate(args, W, sbp, torch, np, dev):
                         "p95": float(np.quantile(err, 0.95)), "max": float(np.max(err))},
         "calibration_rel_l2_mean": float(np.mean(val_err)),
         "mean_trace_rel_l2_mean": float(np.mean(err_mean_trace)),
-        "fallback": {"score": "RMS of d", "threshold": None if not np.isfinite(sur.tau) else float(sur.tau),
+        "fallback": {"score": "relative L2 spread of the %d networks' predictions (a predicted error)"
+                              % len(sur.nets),
+                     "threshold": None if not np.isfinite(sur.tau) else float(sur.tau),
+                     "spearman_score_vs_error": round(spearman, 3),
                      "accepted": int(acc.sum()), "rejected": int((~acc).sum()),
+                     "accepted_rel_l2_mean": float(np.mean(err[acc])) if acc.any() else None,
+                     "accepted_rel_l2_p95": float(np.quantile(err[acc], 0.95)) if acc.any() else None,
                      "accepted_rel_l2_max": float(np.max(err[acc])) if acc.any() else None,
-                     "accepted_within_5pct": float(np.mean(err[acc] <= 0.05)) if acc.any() else None},
+                     "accepted_within_5pct": float(np.mean(err[acc] <= 0.05)) if acc.any() else None,
+                     "rejected_rel_l2_mean": float(np.mean(err[~acc])) if (~acc).any() else None,
+                     "budgets": sweep},
+        "roofline": {"bound": bound, "kernel": "gemm_kernel (all GEMMs of one training step, 8 media)",
+                     "achieved": round(gbs if bound == "hbm" else tflops, 1),
+                     "peak": PEAK_HBM_GBS if bound == "hbm" else PEAK_BF16_TFLOPS,
+                     "unit": "GB/s" if bound == "hbm" else "TFLOP/s",
+                     "frac": round((gbs / PEAK_HBM_GBS) if bound == "hbm" else (tflops / PEAK_BF16_TFLOPS), 4),
+                     "traffic": None, "gemm_calls": gs["calls"], "gemm_ms": round(gs["ms"], 3),
+                     "flops": gs["flops"], "algorithmic_bytes": gs["bytes"], "flop_per_byte": round(ai, 2),
+                     "tflops": round(tflops, 2), "gbs": round(gbs, 1)},
         "train_s": round(train_s, 2),
         "data_generation_s": round(gen_s, 2),
         "final_train_loss": hist[-1] if hist else None,
@@ -464,6 +509,7 @@ def main():
     ap.add_argument("--sur-epochs", type=int, default=30, help="training epochs (surrogate workload)")
     ap.add_argument("--sur-T", type=int, default=512, help="time samples per trace (surrogate workload)")
     ap.add_argument("--sur-amp", type=float, default=0.02, help="max |d| of the media (surrogate workload)")
+    ap.add_argument("--sur-members", type=int, default=2, help="networks in the ensemble (surrogate workload)")
     ap.add_argument("--adjoint-steps", type=int, default=1500, help="steps of the adjoint workload")
     ap.add_argument("--every", type=int, default=100, help="checkpoint interval of the adjoint workload")
     ap.add_argument("--warmup-grad", type=int, default=1, help="untimed short gradient runs (adjoint workload)")

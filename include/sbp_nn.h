@@ -47,10 +47,12 @@ int sbp_nn_act_bwd(long long n, const float* z, const float* dh, float* dz, int 
 
 /*
  * out[c] = sum over s < S and p < P of x[s][c][p] (times w[s][p] if w is not
- * NULL), accumulated in double in a fixed order; added to out if accumulate.
+ * NULL), accumulated in double in a fixed order (the same result on every
+ * call); added to out if accumulate.  part: caller-owned device workspace of
+ * 64 * C doubles (partial sums), overwritten.  C <= 65535.
  */
 int sbp_nn_channel_sum(int S, int C, long long P, const float* x, const float* w, float* out, int accumulate,
-                       void* stream);
+                       double* part, void* stream);
 
 /* h[s][c][p] = w[c] x[s][p] + b[c] (the lifting layer). */
 int sbp_nn_lift(int S, int C, long long P, const float* x, const float* w, const float* b, float* h, void* stream);

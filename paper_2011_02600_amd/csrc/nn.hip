@@ -28,6 +28,14 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // 16-byte LDS read.  Lane l of a 16 x 16 x 32 tile supplies A row l % 16 and
 // B column l % 16 at k = 8 (l / 16) .. 8 (l / 16) + 7, and receives C rows
 // 4 (l / 16) .. 4 (l / 16) + 3 of column l % 16.
+//
+// Each K-step's operand tiles (64 rows x 32 k, 8 values per thread) are
+// loaded into registers while the previous step's matrix-core work runs and
+// then stored to the other of two LDS buffers (one barrier per step).  A tile
+// is loaded 16 bytes at a time along its unit-stride index when that index is
+// k (MODE 1) or the row index (MODE 2) and the addresses are 16-byte aligned
+// (checked on the host), else one element at a time along the unit-stride
+// index (MODE 0).
 constexpr int BM = 64, BN = 64, BK = 32, KP = BK + 8;  // KP: padded row (bf16), 80 bytes
 
 struct GemmArgs {
@@ -41,9 +49,83 @@ struct GemmArgs {
   long long sCb, sCm, sCn;
 };
 
+typedef float f32x4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+// tile rows r0 .. r0+63 (m of A, n of B) x k0 .. k0+31 of an operand with
+// element strides s_row, s_k, R rows and K columns in all
+template <int MODE>
+__device__ __forceinline__ void gemm_load(const float* X, long long s_row, long long s_k, int R, int K, int r0,
+                                          int k0, int tid, bool kfast, float v[8]) {
+  if constexpr (MODE == 1) {  // float4 along k (s_k == 1)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int g = tid + 256 * h, r = r0 + (g >> 3), k = k0 + (g & 7) * 4;
+      if (r < R && k + 3 < K) {
+        const f32x4v x = *reinterpret_cast<const f32x4v*>(X + r * s_row + k);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[4 * h + i] = x[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[4 * h + i] = (r < R && k + i < K) ? X[r * s_row + (k + i)] : 0.f;
+      }
+    }
+  } else if constexpr (MODE == 2) {  // float4 along the row index (s_row == 1)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int g = tid + 256 * h, k = k0 + (g >> 4), r = r0 + (g & 15) * 4;
+      if (k < K && r + 3 < R) {
+        const f32x4v x = *reinterpret_cast<const f32x4v*>(X + k * s_k + r);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[4 * h + i] = x[i];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[4 * h + i] = (k < K && r + i < R) ? X[k * s_k + (r + i)] : 0.f;
+      }
+    }
+  } else {  // one element at a time, the unit-stride index fastest across threads
+#pragma unroll
+    for (int e8 = 0; e8 < 8; ++e8) {
+      const int e = tid + 256 * e8;
+      const int rr = kfast ? e / BK : e % 64;
+      const int kk = kfast ? e % BK : e / 64;
+      const int r = r0 + rr, k = k0 + kk;
+      v[e8] = (r < R && k < K) ? X[r * s_row + k * s_k] : 0.f;
+    }
+  }
+}
+
+template <int MODE>
+__device__ __forceinline__ void gemm_store(__bf16* S, const float v[8], int tid, bool kfast) {
+  if constexpr (MODE == 1) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int g = tid + 256 * h, rr = g >> 3, kq = (g & 7) * 4;
+      const bf16x4 w = {(__bf16)v[4 * h], (__bf16)v[4 * h + 1], (__bf16)v[4 * h + 2], (__bf16)v[4 * h + 3]};
+      *reinterpret_cast<bf16x4*>(&S[rr * KP + kq]) = w;
+    }
+  } else if constexpr (MODE == 2) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int g = tid + 256 * h, kk = g >> 4, rq = (g & 15) * 4;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) S[(rq + i) * KP + kk] = (__bf16)v[4 * h + i];
+    }
+  } else {
+#pragma unroll
+    for (int e8 = 0; e8 < 8; ++e8) {
+      const int e = tid + 256 * e8;
+      const int rr = kfast ? e / BK : e % 64;
+      const int kk = kfast ? e % BK : e / 64;
+      S[rr * KP + kk] = (__bf16)v[e8];
+    }
+  }
+}
+
+template <int AM, int BMODE>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) __bf16 As[BM * KP];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[BN * KP];
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][BM * KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][BN * KP];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -52,52 +134,46 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g) {
   const float* A = g.A + b * g.sAb;
   const float* B = g.B + b * g.sBb;
   float* C = g.C + b * g.sCb;
-  // staging order: the unit-stride index runs fastest across threads
+  // scalar staging order: the unit-stride index runs fastest across threads
   const bool a_kfast = g.sAk == 1 || g.sAm != 1;
-  const bool b_nfast = g.sBn == 1 || g.sBk != 1;
+  const bool b_kfast = !(g.sBn == 1 || g.sBk != 1);
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+  float ra[8], rb[8];
+  gemm_load<AM>(A, g.sAm, g.sAk, g.M, g.K, m0, 0, tid, a_kfast, ra);
+  gemm_load<BMODE>(B, g.sBn, g.sBk, g.N, g.K, n0, 0, tid, b_kfast, rb);
+  int buf = 0;
   for (int k0 = 0; k0 < g.K; k0 += BK) {
-#pragma unroll
-    for (int r = 0; r < (BM * BK) / 256; ++r) {
-      const int e = tid + r * 256;
-      const int mm = a_kfast ? e / BK : e % BM;
-      const int kk = a_kfast ? e % BK : e / BM;
-      const int m = m0 + mm, k = k0 + kk;
-      const float v = (m < g.M && k < g.K) ? A[m * g.sAm + k * g.sAk] : 0.f;
-      As[mm * KP + kk] = (__bf16)v;
-    }
-#pragma unroll
-    for (int r = 0; r < (BN * BK) / 256; ++r) {
-      const int e = tid + r * 256;
-      const int nn = b_nfast ? e % BN : e / BK;
-      const int kk = b_nfast ? e / BN : e % BK;
-      const int n = n0 + nn, k = k0 + kk;
-      const float v = (n < g.N && k < g.K) ? B[k * g.sBk + n * g.sBn] : 0.f;
-      Bs[nn * KP + kk] = (__bf16)v;
-    }
+    // the buffer written here was last read two steps ago, before the
+    // barrier of the previous step
+    gemm_store<AM>(As[buf], ra, tid, a_kfast);
+    gemm_store<BMODE>(Bs[buf], rb, tid, b_kfast);
     __syncthreads();
+    if (k0 + BK < g.K) {  // the next step's tiles, in flight during this step's matrix-core work
+      gemm_load<AM>(A, g.sAm, g.sAk, g.M, g.K, m0, k0 + BK, tid, a_kfast, ra);
+      gemm_load<BMODE>(B, g.sBn, g.sBk, g.N, g.K, n0, k0 + BK, tid, b_kfast, rb);
+    }
     const int kq = 8 * (lane >> 4);
     bf16x8 af[2], bfr[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int row = wm * 32 + i * 16 + (lane & 15);
-      af[i] = *reinterpret_cast<const bf16x8*>(&As[row * KP + kq]);
+      af[i] = *reinterpret_cast<const bf16x8*>(&As[buf][row * KP + kq]);
     }
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int col = wn * 32 + j * 16 + (lane & 15);
-      bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[col * KP + kq]);
+      bfr[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][col * KP + kq]);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
-    __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -114,6 +190,25 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmArgs g) {
         }
       }
     }
+}
+
+// staging mode of an operand (see gemm_kernel): 1 if k has unit stride, 2 if
+// the row index has, each only when every 4-element group is 16-byte aligned
+int gemm_mode(const float* X, long long sb, long long s_row, long long s_k) {
+  const bool al = ((std::uintptr_t)X % 16) == 0 && sb % 4 == 0;
+  if (al && s_k == 1 && s_row % 4 == 0) return 1;
+  if (al && s_row == 1 && s_k % 4 == 0) return 2;
+  return 0;
+}
+
+template <int AM>
+void gemm_launch_b(int bm, dim3 grid, hipStream_t st, const GemmArgs& g) {
+  if (bm == 1)
+    hipLaunchKernelGGL((gemm_kernel<AM, 1>), grid, dim3(256), 0, st, g);
+  else if (bm == 2)
+    hipLaunchKernelGGL((gemm_kernel<AM, 2>), grid, dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL((gemm_kernel<AM, 0>), grid, dim3(256), 0, st, g);
 }
 
 // ---------------------------------------------------------------------------
@@ -145,25 +240,47 @@ __global__ void act_bwd_kernel(long long n, const float* z, const float* dh, flo
     dz[e] = act ? dh[e] * gelu_grad(z[e]) : dh[e];
 }
 
-// out[c] (+)= sum over s, p of x[s][c][p] (times w[s][p] if w): one block per
-// channel, fixed-order tree reduction (deterministic)
-__global__ __launch_bounds__(1024) void channel_sum_kernel(int S, int C, long long P, const float* x, const float* w,
-                                                           float* out, int accumulate) {
-  __shared__ double red[1024];
-  const int c = blockIdx.x;
-  double acc = 0.0;
-  for (int s = 0; s < S; ++s) {
-    const float* xs = x + ((long long)s * C + c) * P;
-    const float* ws = w ? w + (long long)s * P : nullptr;
-    for (long long p = threadIdx.x; p < P; p += blockDim.x) acc += ws ? (double)xs[p] * ws[p] : (double)xs[p];
+// out[c] (+)= sum over s, p of x[s][c][p] (times w[s][p] if w), in two
+// passes with fixed orders (deterministic): block (c, j) of the first sums
+// slice j of channel c's S * P values (four interleaved double accumulators
+// per thread, then a tree) into part[c * kChanSplit + j]; the second adds a
+// channel's kChanSplit partial sums in order.
+constexpr int kChanSplit = 64;
+
+__global__ __launch_bounds__(256) void channel_part_kernel(int S, int C, long long P, const float* x, const float* w,
+                                                           double* part) {
+  __shared__ double red[256];
+  const int c = blockIdx.x, j = blockIdx.y;
+  const long long n = (long long)S * P;
+  const long long per = (n + kChanSplit - 1) / kChanSplit;
+  const long long e0 = (long long)j * per, e1 = e0 + per < n ? e0 + per : n;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (long long e = e0 + threadIdx.x; e < e1; e += 4 * 256) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const long long f = e + (long long)u * 256;
+      if (f < e1) {
+        const long long s = f / P, p = f - s * P;
+        const double v = x[(s * C + c) * P + p];
+        acc[u] += w ? v * (double)w[s * P + p] : v;
+      }
+    }
   }
-  red[threadIdx.x] = acc;
+  red[threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   __syncthreads();
-  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+  for (int st = 128; st > 0; st >>= 1) {
     if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[c] = (float)(accumulate ? out[c] + red[0] : red[0]);
+  if (threadIdx.x == 0) part[(long long)c * kChanSplit + j] = red[0];
+}
+
+__global__ void channel_sum_kernel(int C, const double* part, float* out, int accumulate) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  double v = 0.0;
+  for (int j = 0; j < kChanSplit; ++j) v += part[(long long)c * kChanSplit + j];
+  out[c] = (float)(accumulate ? out[c] + v : v);
 }
 
 // h[s][c][p] = w[c] x[s][p] + b[c]
@@ -204,12 +321,30 @@ __global__ void add_rows_kernel(int S, long long n, const float* b, float* y) {
     y[e] += b[e % n];
 }
 
-// out[i] (+)= sum over rows s of x[s][i]
-__global__ void sum_rows_kernel(int S, long long n, const float* x, float* out, int accumulate) {
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    float a = 0.f;
-    for (int s = 0; s < S; ++s) a += x[(long long)s * n + i];
-    out[i] = accumulate ? out[i] + a : a;
+// out[i] (+)= sum over rows s of x[s][i].  A block covers 32 columns with 8
+// row lanes: lane g sums rows g, g + 8, g + 16, ... into four interleaved
+// accumulators (loads in flight together), and the 8 lane sums of a column
+// are added in lane order (a fixed order: the same result on every call).
+__global__ __launch_bounds__(256) void sum_rows_kernel(int S, long long n, const float* x, float* out, int accumulate) {
+  __shared__ float red[8][32];
+  const int ci = threadIdx.x & 31, g = threadIdx.x >> 5;
+  const long long i = blockIdx.x * 32LL + ci;
+  float a[4] = {0.f, 0.f, 0.f, 0.f};
+  if (i < n) {
+    int s = g;
+    for (; s + 24 < S; s += 32) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] += x[(long long)(s + 8 * u) * n + i];
+    }
+    for (; s < S; s += 8) a[0] += x[(long long)s * n + i];
+  }
+  red[g][ci] = (a[0] + a[1]) + (a[2] + a[3]);
+  __syncthreads();
+  if (g == 0 && i < n) {
+    float v = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v += red[k][ci];
+    out[i] = accumulate ? out[i] + v : v;
   }
 }
 
@@ -355,7 +490,14 @@ int sbp_nn_gemm(int batch, int M, int N, int K, float alpha, const float* A, lon
   if ((M + BM - 1) / BM > 65535) return nn_fail("M too large");
   GemmArgs g{M, N, K, alpha, beta, A, sAb, sAm, sAk, B, sBb, sBk, sBn, C, sCb, sCm, sCn};
   dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, batch);
-  hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, (hipStream_t)stream, g);
+  const int am = gemm_mode(A, sAb, sAm, sAk), bm = gemm_mode(B, sBb, sBn, sBk);
+  const hipStream_t st = (hipStream_t)stream;
+  if (am == 1)
+    gemm_launch_b<1>(bm, grid, st, g);
+  else if (am == 2)
+    gemm_launch_b<2>(bm, grid, st, g);
+  else
+    gemm_launch_b<0>(bm, grid, st, g);
   return nn_status();
 }
 
@@ -377,9 +519,12 @@ int sbp_nn_act_bwd(long long n, const float* z, const float* dh, float* dz, int 
 }
 
 int sbp_nn_channel_sum(int S, int C, long long P, const float* x, const float* w, float* out, int accumulate,
-                       void* stream) {
-  if (S < 0 || C <= 0 || P <= 0 || !x || !out) return nn_fail("invalid channel_sum arguments");
-  hipLaunchKernelGGL(channel_sum_kernel, dim3(C), dim3(1024), 0, (hipStream_t)stream, S, C, P, x, w, out, accumulate);
+                       double* part, void* stream) {
+  if (S < 0 || C <= 0 || P <= 0 || !x || !out || !part) return nn_fail("invalid channel_sum arguments");
+  if (C > 65535) return nn_fail("channel_sum: C must be <= 65535");
+  const hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(channel_part_kernel, dim3(C, kChanSplit), dim3(256), 0, st, S, C, P, x, w, part);
+  hipLaunchKernelGGL(channel_sum_kernel, dim3((C + 255) / 256), dim3(256), 0, st, C, part, out, accumulate);
   return nn_status();
 }
 
@@ -417,7 +562,8 @@ int sbp_nn_add_rows(int S, long long n, const float* b, float* y, void* stream) 
 
 int sbp_nn_sum_rows(int S, long long n, const float* x, float* out, int accumulate, void* stream) {
   if (S < 0 || n <= 0 || !x || !out) return nn_fail("invalid sum_rows arguments");
-  hipLaunchKernelGGL(sum_rows_kernel, dim3(blocks_for(n)), dim3(256), 0, (hipStream_t)stream, S, n, x, out,
+  if ((n + 31) / 32 > 0x7fffffffLL) return nn_fail("sum_rows: n too large");
+  hipLaunchKernelGGL(sum_rows_kernel, dim3((unsigned)((n + 31) / 32)), dim3(256), 0, (hipStream_t)stream, S, n, x, out,
                      accumulate);
   return nn_status();
 }

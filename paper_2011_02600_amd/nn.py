@@ -42,7 +42,7 @@ def lib():
                             c_float, c_void_p, c_ll, c_ll, c_ll, c_void_p],
             "sbp_nn_bias_act": [c_int, c_int, c_ll, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p],
             "sbp_nn_act_bwd": [c_ll, c_void_p, c_void_p, c_void_p, c_int, c_void_p],
-            "sbp_nn_channel_sum": [c_int, c_int, c_ll, c_void_p, c_void_p, c_void_p, c_int, c_void_p],
+            "sbp_nn_channel_sum": [c_int, c_int, c_ll, c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p],
             "sbp_nn_lift": [c_int, c_int, c_ll, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p],
             "sbp_nn_gather": [c_int, c_int, c_ll, c_int, c_void_p, c_void_p, c_void_p, c_void_p],
             "sbp_nn_scatter": [c_int, c_int, c_ll, c_int, c_void_p, c_void_p, c_void_p, c_void_p],
@@ -73,13 +73,45 @@ def _p(t):
     return None if t is None else t.data_ptr()
 
 
+_gemm_log = None
+
+
+def gemm_profile(on):
+    """Start (True) or stop (False) recording every gemm call: its flops
+    (2 M N K per batch entry), its algorithmic bytes (A, B and C once, C
+    twice when accumulated, 4 bytes each) and a pair of events on its
+    stream.  Returns the records of the stopped recording."""
+    global _gemm_log
+    out = _gemm_log
+    _gemm_log = [] if on else None
+    return out
+
+
+def gemm_profile_summary(records):
+    """Totals of gemm_profile records (after a synchronisation): calls,
+    flops, bytes, milliseconds."""
+    ms = sum(e0.elapsed_time(e1) for (_, _, e0, e1) in records)
+    return {"calls": len(records), "flops": float(sum(r[0] for r in records)),
+            "bytes": float(sum(r[1] for r in records)), "ms": ms}
+
+
 def gemm(A, B, C, M, N, K, sA, sB, sC, batch=1, alpha=1.0, beta=0.0, stream=None, offs=(0, 0, 0)):
     """C[b] = alpha A[b] B[b] + beta C[b]; sA = (sAb, sAm, sAk), sB = (sBb, sBk,
     sBn), sC = (sCb, sCm, sCn) element strides; offs: element offsets into
     the three tensors."""
     es = 4
+    rec = _gemm_log is not None
+    if rec:
+        import torch
+        st = torch.cuda.ExternalStream(stream) if stream else torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
     _ck(lib().sbp_nn_gemm(batch, M, N, K, alpha, A.data_ptr() + es * offs[0], *sA, B.data_ptr() + es * offs[1], *sB,
                           beta, C.data_ptr() + es * offs[2], *sC, stream))
+    if rec:
+        e1.record(st)
+        nbytes = es * batch * (M * K + K * N + M * N * (2 if beta != 0.0 else 1))
+        _gemm_log.append((2.0 * batch * M * N * K, nbytes, e0, e1))
 
 
 def cosine_basis(n, m):
@@ -120,6 +152,7 @@ class SpectralOperator:
         self.adam_v = {k: torch.zeros_like(v) for k, v in p.items()}
         self.step_count = 0
         self._part = torch.zeros(256, dtype=torch.float64, device=self.dev)
+        self._cpart = torch.zeros(64 * width, dtype=torch.float64, device=self.dev)  # channel sums
         self._bufs = {}
 
     # ---- buffers --------------------------------------------------------------
@@ -226,7 +259,7 @@ class SpectralOperator:
             act = 1 if l < L - 1 else 0
             dz = self._buf("dz", (S, C, P))
             _ck(lb.sbp_nn_act_bwd(S * C * P, _p(self.zs[l]), _p(dh), _p(dz), act, st))
-            _ck(lb.sbp_nn_channel_sum(S, C, P, _p(dz), None, _p(g["b%d" % l]), 0, st))
+            _ck(lb.sbp_nn_channel_sum(S, C, P, _p(dz), None, _p(g["b%d" % l]), 0, _p(self._cpart), st))
             h = self.hs[l]
             # pointwise path u = W h: dW = sum_s dz_s h_s^T, dh = W^T dz
             self._weight_grad(dz, h, g["W%d" % l])
@@ -243,15 +276,17 @@ class SpectralOperator:
             self._inv_T(dxh, S, dhn, "b", beta=1.0)
             dh, self._bufs["dh"], self._bufs["dhn"] = dhn, dhn, dh
         # lift: h0 = w x + b
-        _ck(lb.sbp_nn_channel_sum(S, C, P, _p(dh), _p(self.x), _p(g["w_lift"]), 0, st))
-        _ck(lb.sbp_nn_channel_sum(S, C, P, _p(dh), None, _p(g["b_lift"]), 0, st))
+        _ck(lb.sbp_nn_channel_sum(S, C, P, _p(dh), _p(self.x), _p(g["w_lift"]), 0, _p(self._cpart), st))
+        _ck(lb.sbp_nn_channel_sum(S, C, P, _p(dh), None, _p(g["b_lift"]), 0, _p(self._cpart), st))
 
     def _weight_grad(self, dz, h, out):
         """out (C x C) = sum_s dz_s h_s^T: the long contraction over the grid is
-        split into chunks of at most 4096 points (one GEMM batch entry each)
-        whose partial products are summed afterwards."""
+        split into chunks (one GEMM batch entry, i.e. one thread block, each)
+        whose partial products are summed afterwards; chunks of 512 points
+        when the grid has at least 128 of them, so that a call fills the
+        GPU, else one chunk."""
         S, C, P = self.S, self.C, self.P
-        PC = P if P <= 4096 or P % 4096 else 4096
+        PC = 512 if P % 512 == 0 and P // 512 >= 128 else P
         nch = P // PC
         parts = self._buf("wparts", (S * nch, C, C))
         for s in range(S):

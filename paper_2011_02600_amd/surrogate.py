@@ -4,12 +4,15 @@ fallback to the solver.
 
 The solver produces every sample: for a material perturbation field d on an
 n^3 grid (cp and cs scaled by 1 + d, rho fixed), sbp_step_batch runs the
-shots and the receivers record v_z after every step.  The network maps d
-(scaled to unit amplitude) to the normalised traces.  At prediction time a
-sample is answered by the network when its fallback score -- the RMS of d --
-lies at or below a threshold calibrated on held-out training samples so that
-the accepted ones stay within the error budget; otherwise the solver runs.
-Orchestration only: the solver and the network run in the HIP library.
+shots and the receivers record v_z after every step.  An ensemble of
+networks (same data, different initialisations and sample orders) maps d
+(scaled to unit amplitude) to the normalised traces; the prediction is
+their mean.  The fallback score of a sample is a predicted error: the
+relative spread of the ensemble's predictions.  A sample is answered by the
+ensemble when its score lies at or below a threshold calibrated on held-out
+training samples so that the accepted ones stay within the error budget;
+otherwise the solver runs.  Orchestration only: the solver and the
+networks run in the HIP library.
 """
 import time
 
@@ -57,13 +60,16 @@ def solve_batch(sbp, torch, case, fields, dev, nmax=64, log=None):
 
 
 class Surrogate:
-    """Spectral operator + normalisation + fallback threshold."""
+    """An ensemble of spectral operators + normalisation + fallback
+    threshold on the ensemble's spread."""
 
-    def __init__(self, nn, torch, case, dev, modes=8, width=32, layers=4, seed=0):
+    def __init__(self, nn, torch, case, dev, modes=8, width=32, layers=4, seed=0, members=2):
         self.torch, self.case, self.dev = torch, case, dev
         n = case["n"]
         pos = [k * n * n + j * n + i for (i, j, k) in case["receivers"]]
-        self.net = nn.SpectralOperator(n, modes, width, layers, pos, case["T"], device=dev, seed=seed)
+        self.nets = [nn.SpectralOperator(n, modes, width, layers, pos, case["T"], device=dev, seed=seed + 101 * e)
+                     for e in range(members)]
+        self.net = self.nets[0]
         self.xscale = 1.0 / case["amp"]
         self.yscale = 1.0
         self.ymean = 0.0
@@ -73,61 +79,84 @@ class Surrogate:
         return d * self.xscale
 
     def train(self, d, y, epochs=20, batch=8, lr=2e-3, log=None):
-        """d: (N, n, n, n) device tensor of perturbations; y: (N, R, T) traces."""
+        """d: (N, n, n, n) device tensor of perturbations; y: (N, R, T) traces.
+        Every member sees every sample each epoch, in its own order."""
         torch = self.torch
         N = d.shape[0]
-        # the network predicts the deviation from the mean training trace
+        # the networks predict the deviation from the mean training trace
         self.ymean = y.mean(dim=0)
         self.yscale = float((y - self.ymean).std())
         yn = (y - self.ymean) / self.yscale
-        rng = np.random.default_rng(0)
         steps = epochs * (N // batch)
-        k = 0
         hist = []
-        for ep in range(epochs):
-            order = rng.permutation(N)
-            tot = 0.0
-            for b0 in range(0, N - batch + 1, batch):
-                idx = torch.tensor(order[b0:b0 + batch], device=self.dev)
-                x = self._x(d[idx]).contiguous()
-                t = yn[idx].contiguous()
-                out = self.net.forward(x)
-                loss, dy = self.net.loss(out, t, scale=1.0 / batch)
-                self.net.backward(dy)
-                # cosine learning-rate decay
-                self.net.adam_step(lr * 0.5 * (1 + np.cos(np.pi * k / steps)))
-                tot += loss
-                k += 1
-            hist.append(tot / (N // batch))
-            if log:
-                log("surrogate: epoch %d loss %.5f" % (ep, hist[-1]))
+        for e, net in enumerate(self.nets):
+            rng = np.random.default_rng(1000 + e)
+            k = 0
+            for ep in range(epochs):
+                order = rng.permutation(N)
+                tot = 0.0
+                for b0 in range(0, N - batch + 1, batch):
+                    idx = torch.tensor(order[b0:b0 + batch], device=self.dev)
+                    x = self._x(d[idx]).contiguous()
+                    t = yn[idx].contiguous()
+                    out = net.forward(x)
+                    loss, dy = net.loss(out, t, scale=1.0 / batch)
+                    net.backward(dy)
+                    # cosine learning-rate decay
+                    net.adam_step(lr * 0.5 * (1 + np.cos(np.pi * k / steps)))
+                    tot += loss
+                    k += 1
+                if e == 0:
+                    hist.append(tot / (N // batch))
+                if log:
+                    log("surrogate: member %d epoch %d loss %.5f" % (e, ep, tot / (N // batch)))
         return hist
 
-    def predict(self, d, batch=8):
+    def _members(self, d, batch=8):
+        """Each member's denormalised prediction: (members, N, R, T)."""
         torch = self.torch
         outs = []
-        for b0 in range(0, d.shape[0], batch):
-            x = self._x(d[b0:b0 + batch]).contiguous()
-            outs.append(self.net.forward(x).clone())
-        return torch.cat(outs) * self.yscale + self.ymean
+        for net in self.nets:
+            parts = []
+            for b0 in range(0, d.shape[0], batch):
+                x = self._x(d[b0:b0 + batch]).contiguous()
+                parts.append(net.forward(x).clone())
+            outs.append(torch.cat(parts) * self.yscale + self.ymean)
+        return torch.stack(outs)
+
+    def predict_with_score(self, d, batch=8):
+        """(ensemble mean prediction, fallback score per sample): the score is
+        the relative L2 spread of the members around their mean."""
+        p = self._members(d, batch)
+        mean = p.mean(dim=0)
+        spread = ((p - mean) ** 2).sum(dim=(2, 3)).mean(dim=0).sqrt()
+        score = (spread / (mean ** 2).sum(dim=(1, 2)).sqrt()).double().cpu().numpy()
+        return mean, score
+
+    def predict(self, d, batch=8):
+        return self.predict_with_score(d, batch)[0]
 
     @staticmethod
     def rel_err(pred, true):
         num = ((pred - true) ** 2).sum(dim=(1, 2)).sqrt()
         return (num / (true ** 2).sum(dim=(1, 2)).sqrt()).double().cpu().numpy()
 
-    def score(self, d):
-        return (d.double() ** 2).mean(dim=(1, 2, 3)).sqrt().cpu().numpy()
+    @staticmethod
+    def threshold(err, sc, budget=0.05, quantile=0.95):
+        """Largest score threshold whose accepted samples (score <= threshold)
+        keep the `quantile` of their relative errors within `budget`; -inf if
+        none does."""
+        order = np.argsort(sc)
+        tau = -np.inf
+        for i in range(1, len(order) + 1):
+            if np.quantile(err[order[:i]], quantile) <= budget:
+                tau = sc[order[i - 1]]
+        return tau
 
     def calibrate(self, d_val, y_val, budget=0.05, quantile=0.95):
-        """Largest score threshold whose accepted validation samples keep the
-        `quantile` of their relative errors within `budget`."""
-        err = self.rel_err(self.predict(d_val), y_val)
-        sc = self.score(d_val)
-        order = np.argsort(sc)
-        self.tau = -np.inf
-        for i in range(1, len(order) + 1):
-            acc = err[order[:i]]
-            if np.quantile(acc, quantile) <= budget:
-                self.tau = sc[order[i - 1]]
+        """Sets the threshold from validation samples (see threshold);
+        returns their errors and scores."""
+        pred, sc = self.predict_with_score(d_val)
+        err = self.rel_err(pred, y_val)
+        self.tau = self.threshold(err, sc, budget, quantile)
         return err, sc

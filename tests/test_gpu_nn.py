@@ -1,6 +1,8 @@
 """GPU checks of the surrogate kernels (include/sbp_nn.h): the BF16
 matrix-core GEMM against a float64 product of the bf16-rounded operands
-(strided, transposed, batched and ragged cases), and the spectral neural
+(strided, transposed, batched and ragged cases, each operand staged 16
+bytes at a time along k, along its rows, or one element at a time), and the
+spectral neural
 operator's forward and backward passes against the float64 reference
 network (oracle/fno.py) on the same parameters and inputs.
 
@@ -41,6 +43,10 @@ GEMM_CASES = [
     (3, 40, 50, 31, True, True, 0.5),
     (5, 8, 8, 4097, False, True, 0.0),
     (2, 3000, 8, 64, False, False, 0.0),
+    # 16-byte staging along k for both operands with a ragged K and ragged
+    # rows; along the row index for both
+    (2, 50, 36, 44, False, True, 0.0),
+    (1, 52, 60, 40, True, False, 1.0),
 ]
 
 
@@ -147,3 +153,10 @@ def test_surrogate_pipeline_gains_over_the_mean_trace_and_the_solver():
         % (hist[0], hist[-1], float(np.mean(err)), float(np.mean(base)), t_net, t_solver))
     assert np.mean(err) < 0.5 * np.mean(base)
     assert t_net < t_solver
+    # the fallback score: the two networks' spread, finite and positive, and
+    # a calibrated threshold that accepts a sample only within the budget
+    _, score = sur.predict_with_score(d[128:])
+    assert np.all(np.isfinite(score)) and np.all(score > 0)
+    verr, vsc = sur.calibrate(d[112:128], y[112:128], budget=0.5)
+    acc = vsc <= sur.tau
+    assert acc.any() and np.quantile(verr[acc], 0.95) <= 0.5
