@@ -372,7 +372,7 @@ def run_orders(args, W, sbp, torch, np, dev):
         return out, el
 
     res = {}
-    for order in (2, 3, 4, 5, 6, 7):
+    for order in (2, 3, 4, 5, 6, 7, 8):
         # reference: the same order on the refined grid (self-convergence,
         # the same yardstick for every order)
         ref, _ = traces(fine, order, dt / 2, 2 * nc)
