@@ -4,7 +4,7 @@
  * truncated cosine basis) that maps a material field to receiver traces and
  * is trained on traces the solver itself computes.  Not part of the paper's
  * method: a learned stand-in for the solver, which stays the fallback and
- * the judge of the surrogate's error.
+ * the reference the surrogate's error is measured against.
  *
  * Conventions: device pointers to fp32 arrays owned by the caller; sizes and
  * element strides in elements; every call is asynchronous on `stream` (a
