@@ -8,14 +8,17 @@ plus the receiver gather.  Prints one JSON line.
     python bench.py --workload batched [--steps 100] [--warmup 5]
 
 The metric is Mpts*stage/s (grid points times Runge-Kutta stages per
-second).  A Runge-Kutta stage is two launches: the stage kernel over the
-tiled nodes (all but the last q column and r row) and the edge kernel over
-the rest.  The roofline object reports the stage kernel: algorithmic bytes
-of the nodes one launch computes over its average launch duration, timed by
-the library's events around each launch (sbp_set_profiling), against the
-8 TB/s HBM peak; `traffic` is the HBM bytes per launch from the committed
-rocprofv3 counter summary when that was taken on the current sources.
-cpu_baseline times the CPU oracle on a bounded sample of the same workload.
+second).  A Runge-Kutta stage is the stage kernel over the tiled nodes (all
+but the last q column and r row), the edge kernel over the rest, the
+boundary-penalty kernel and the source kernel.  The roofline object reports
+the stage kernel: algorithmic bytes of the nodes one launch computes over its
+average launch duration, timed by the library's events around each launch
+(sbp_set_profiling), against the 8 TB/s HBM peak and against the copy
+ceiling a plain device copy reaches in the same run; `traffic` is the HBM
+bytes per launch from the committed rocprofv3 counter summary when that was
+taken on the current sources.  The same workload in double precision follows
+as the `fp64` object.  cpu_baseline times the CPU oracle on a bounded sample
+of the same workload.
 
 `--workload batched` measures the batched-shots workload instead (32 cubes
 of uneven size, orders 4 and 6, one sbp_step_batch call): shots per second
@@ -26,7 +29,7 @@ seismograms (64^3 Gaussian-random-field media, 64 receivers x 512 samples)
 and reports its speedup over the solver on held-out media, with the
 fallback to the solver for media outside its calibrated error budget.
 
-`--workload orders` compares the interior orders 2-7 at marginal resolution
+`--workload orders` compares the interior orders 2-8 at marginal resolution
 on the topography geometry against 2x refined runs of the same order.
 
 `--workload adjoint` measures the material gradient (sbp_gradient): the
@@ -94,6 +97,26 @@ def read_traffic(key="hbm_bytes_per_launch"):
         return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def copy_ceiling(torch, dev, mib=1024, reps=10):
+    """HBM bandwidth a plain device copy reaches on this GPU (read + write
+    bytes over the time of `reps` copies of `mib` MiB, events on the current
+    stream): the streaming ceiling the stage kernel is compared with."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * 4 * n * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    return gbs
 
 
 def cpu_baseline(wl, order=6, nstages=5):
@@ -559,6 +582,7 @@ def main():
     nodes = nq * nr * ns
     order = args.order
     m = measure_topo(args, wl, args.dtype, order, sbp, torch, np, dev)
+    ceiling = copy_ceiling(torch, dev)
     traffic = read_traffic() if order == 6 and args.dtype == "f32" else None
     out = {
         "metric": "Mpts*stage/s (order-%d %s curvilinear RHS + LSRK4 stage update)"
@@ -582,7 +606,9 @@ def main():
                    "launch": {"ty": args.ty, "zchunk": args.zchunk}},
         "roofline": dict(m["roofline"], traffic=None if traffic is None else int(traffic),
                          traffic_rate_gbs=None if traffic is None
-                         else round(traffic / (m["roofline"]["avg_launch_ms"] / 1e3) / 1e9, 1)),
+                         else round(traffic / (m["roofline"]["avg_launch_ms"] / 1e3) / 1e9, 1),
+                         copy_ceiling_gbs=round(ceiling, 1),
+                         frac_of_copy_ceiling=round(m["roofline"]["achieved"] / ceiling, 4)),
     }
     if not args.no_fp64 and args.dtype == "f32" and order <= 6:  # order 7 is built in FP32 only
         # the same workload in the paper's arithmetic (double precision)
@@ -590,7 +616,9 @@ def main():
         t64 = read_traffic("hbm_bytes_per_launch_f64") if order == 6 else None
         r64 = dict(m64["roofline"], traffic=None if t64 is None else int(t64),
                    traffic_rate_gbs=None if t64 is None
-                   else round(t64 / (m64["roofline"]["avg_launch_ms"] / 1e3) / 1e9, 1))
+                   else round(t64 / (m64["roofline"]["avg_launch_ms"] / 1e3) / 1e9, 1),
+                   copy_ceiling_gbs=round(ceiling, 1),
+                   frac_of_copy_ceiling=round(m64["roofline"]["achieved"] / ceiling, 4))
         out["fp64"] = {"value": m64["value"], "unit": "Mpts*stage/s", "ms_per_step": m64["ms_per_step"],
                        "steps": args.steps, "roofline": r64}
     if not args.no_cpu:
