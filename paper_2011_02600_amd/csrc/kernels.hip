@@ -225,7 +225,7 @@ struct StageLds {
   static constexpr std::size_t n_tab = kClosureTab * TABN;
   static constexpr std::size_t o_lv = 0, o_lq = o_lv + n_lv, o_lr = o_lq + n_lq, o_ring = o_lr + n_lr,
                                o_sring = o_ring + n_ring, o_tab = o_sring + n_sring, o_tq = o_tab + n_tab,
-                               total = o_tq + n_tq;
+                               o_fq = o_tq + n_tq, total = o_fq + kNumFaceCoef * TY;
   static constexpr std::size_t bytes = total * sizeof(T);
 };
 
@@ -290,6 +290,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
 
   const Arr<T, BUF> gq(A.qin, field), gc(A.coef, field), gd(A.dq, field), go(A.qout, field);
   for (int e = threadIdx.y * 64 + threadIdx.x; e < kClosureTab * TABN; e += NT) ltab[e] = A.tab[e];
+  // q = 0 face coefficients of the plane, one row of kNumFaceCoef per wave
+  T* const lfq = reinterpret_cast<T*>(lds) + L::o_fq;
   // the q weight rows (from the closure table in memory, the right-end rows
   // reversed so that every row runs over ascending columns; D- interior
   // weights with the sign of the difference folded in) and zeroed q windows
@@ -599,14 +601,14 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
         for (int c = 0; c < 6; ++c) pscl[c] = scl_at(c)[cl];
       }
     }
-    // coefficients of the q = 0 face at the wave's row (one address per
-    // wave), loaded when the plane starts and used by the stage update
-    T fcq[Q0S ? kNumFaceCoef : 1];
+    // coefficients of the q = 0 face at the wave's row, loaded when the plane
+    // starts, one per lane (lane kk: coefficient kk), and passed through LDS
+    // to lane 0, which adds the penalty before the stage update
+    T fq_lane = T(0);
     if constexpr (Q0S) {
       if (q0pen) {
         const std::size_t fo = A.face_off[0] + (std::size_t)a * nr + (std::size_t)min(j, nr - 1);
-#pragma unroll
-        for (int kk = 0; kk < kNumFaceCoef; ++kk) fcq[kk] = A.face[fo + (std::size_t)kk * A.face_n[0]];
+        fq_lane = A.face[fo + (std::size_t)min(tx, kNumFaceCoef - 1) * A.face_n[0]];
       }
     }
     // ---------------- phase 1: stage plane a in LDS from the prefetched registers
@@ -670,6 +672,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
       lr[0 * RX * VY + wr] = f[0];
       lr[1 * RX * VY + wr] = f[1];
       lr[2 * RX * VY + wr] = f[2];
+    }
+    if constexpr (Q0S) {
+      if (q0pen && tx < kNumFaceCoef) lfq[ty * kNumFaceCoef + tx] = fq_lane;
     }
     if (xh_in) {  // v and q-flux of the x-halo point
       const T* h = p_hx;
@@ -802,7 +807,12 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
       // the penalty of the q = 0 face at its nodes (single precision); the
       // other boundary penalties are added by penalty_kernel after the launch
       if constexpr (Q0S) {
-        if (q0pen && tx == 0) face_penalty(fcq, A.gamma[0], T(-1), A.traction[0] != 0, v, sg, rate);
+        if (q0pen && tx == 0) {
+          T fcq[kNumFaceCoef];
+#pragma unroll
+          for (int kk = 0; kk < kNumFaceCoef; ++kk) fcq[kk] = lfq[ty * kNumFaceCoef + kk];
+          face_penalty(fcq, A.gamma[0], T(-1), A.traction[0] != 0, v, sg, rate);
+        }
       }
 
       // Runge-Kutta stage update

@@ -181,8 +181,9 @@ hipError_t launch_penalty_batch(const BatchArgs<T>& b, hipStream_t st);
 // Single precision adds the penalty of the q = 0 face inside the stage
 // kernel, at the nodes its tiles compute (lanes i = 0 of the first tiles
 // along q hold the node's values there, while a separate pass would fetch a
-// whole line of every field per node); double precision, short of
-// registers, leaves it to the penalty kernel.
+// whole line of every field per node); in double precision the penalty's
+// arithmetic does not fit beside the derivatives in 256 VGPRs, and the
+// penalty kernel keeps that face.
 template <typename T>
 constexpr bool q0_in_stage() {
   return sizeof(T) == 4;
