@@ -184,6 +184,39 @@ def test_graph_replay_equals_eager_bitwise(dtype):
     assert tma == tmb
 
 
+def test_batched_graph_replay_equals_eager_bitwise():
+    """sbp_step_batch replaying captured step graphs (FP32 work list) gives
+    bitwise the states and receiver traces of the same batch launched step
+    by step (sbp_set_graphs(h, 0) on the first handle), over two calls and
+    more than one source-time table chunk."""
+    say("case: batched graph replay vs eager f32")
+    sbp = sbp_mod()
+    cases = [((19, 17, 21), 4), ((23, 21, 18), 6), ((17, 25, 19), 6)]
+    runs = []
+    for graphs in (True, False):
+        ss, trs, dts = [], [], []
+        for i, (shape, order) in enumerate(cases):
+            ns, nr, nq = shape
+            xyz = W.warped_mesh(nq, nr, ns, seed=60 + i)
+            med = W.random_medium(shape, 70 + i)
+            s = solver(xyz, order, "f32", [0.0, 0.0, 0.0, 0.0, 0.0, 1.0], med)
+            s.add_source((0.4, 0.5, 0.45), (0.0, 0.0, 0.0, 1.0, 0.3, 0.0), 0, 6.0, 0.1)
+            trs.append(s.record(np.array([[2, 3, ns - 1], [nq // 2, nr // 2, ns // 2]]), 600))
+            s.set_state(W.random_state(shape, 80 + i, smooth=True) * 1e-3)
+            dts.append(W.cfl_dt(xyz, med[1], 0.4))
+            ss.append(s)
+        ss[0].set_graphs(graphs)
+        sbp.sbp_step_batch([s.h for s in ss], 17, dts)
+        sbp.sbp_step_batch([s.h for s in ss], 560, dts)
+        torch.cuda.synchronize()
+        runs.append([(s.get_state().cpu().numpy(), t.cpu().numpy(), s.time()) for s, t in zip(ss, trs)])
+        for s in ss:
+            s.close()
+    for (qa, ta, tma), (qb, tb, tmb) in zip(*runs):
+        assert np.isfinite(qa).all() and np.abs(qa).max() > 0
+        assert np.array_equal(qa, qb) and np.array_equal(ta, tb) and tma == tmb
+
+
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_scratch_contents_do_not_matter(dtype):
     """NaN in the next stage's output buffer and in the Runge-Kutta register

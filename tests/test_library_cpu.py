@@ -101,3 +101,14 @@ def test_header_documents_every_entry_point(header):
                 and not lines[-1].lstrip().startswith(("*", "/*")):
             lines.pop()
         assert lines and lines[-1].rstrip().endswith("*/"), n
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU: --gpus 2 exits with status 2 and says
+    so, before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], stdout=subprocess.PIPE,
+                       stderr=subprocess.PIPE, text=True, timeout=300)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
