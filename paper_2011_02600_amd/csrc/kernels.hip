@@ -218,7 +218,17 @@ struct StageLds {
   // 0..M-1 (columns nq-NC .. nq-1 ascending); D+ rows, then D- rows
   static constexpr int QROWS = 2 * S::M + 1;
   static constexpr std::size_t n_tq = 2 * QROWS * NC;
-  static constexpr std::size_t n_lv = 3 * VX * VY, n_lq = 3 * QX * TY, n_lr = 3 * RX * VY, n_ring = QD * 3 * NT;
+  static constexpr std::size_t n_lv = 3 * VX * VY, n_lq = 3 * QX * TY, n_lr = 3 * RX * VY;
+  // s-flux ring: F_s of the QD planes a - Q .. a + R that D-_s at plane a
+  // reads.  Where that ring leaves the LDS short (double precision, order
+  // 7), the newest plane a + R stays in registers and the ring keeps QD - 1
+  // planes (RL)
+  static constexpr bool RL =
+      sizeof(T) == 8 && TY == 8 &&
+      sizeof(T) * (n_lv + n_lq + n_lr + (std::size_t)QD * 3 * NT + kClosureTab * kMaxM * kMaxCols + n_tq) >
+          kLdsBytes;
+  static constexpr int NR = RL ? QD - 1 : QD;
+  static constexpr std::size_t n_ring = (std::size_t)NR * 3 * NT;
   static constexpr std::size_t base_bytes = sizeof(T) * (n_lv + n_lq + n_lr + n_ring);
   static constexpr bool SR = base_bytes + sizeof(T) * SD * 9 * NT <= kLdsBytes;
   static constexpr std::size_t n_sring = SR ? SD * 9 * NT : 1;
@@ -358,7 +368,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
     flux3(m0, m1, m2, sxx, syy, szz, sxy, sxz, syz, f);
   };
   // ring slot of plane k (k >= -Q)
-  auto slot = [&](int k) { return (k + 7 * QD) % QD; };
+  constexpr int NR = L::NR;
+  constexpr bool RL = L::RL;
+  auto slot = [&](int k) { return (k + 7 * NR) % NR; };
 
   __syncthreads();  // closure and weight rows written, windows zeroed
 
@@ -417,7 +429,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   }
 
   // register queue vq[s] = v(a - R + s); ring holds F_s(a - Q .. a + R)
+  // (with RL: a - Q .. a + R - 1, and flead F_s(a + R))
   T vq[3][QD];
+  T flead[RL ? 3 : 1] = {};
 #pragma unroll
   for (int s = 0; s < QD; ++s)
 #pragma unroll
@@ -448,8 +462,13 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
           for (int c = 0; c < 9; ++c) sring[((kf % SD) * 9 + c) * NT + tid] = r[c];
         }
       }
+      if (RL && s == QD - 1) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ring[(slot(kf) * 3 + c) * NT + tid] = f[c];
+        for (int c = 0; c < 3; ++c) flead[RL ? c : 0] = f[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ring[(slot(kf) * 3 + c) * NT + tid] = f[c];
+      }
     }
   }
 
@@ -776,9 +795,19 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
 #pragma unroll
           for (int s = 0; s < QD; ++s) {
             sp += T(S::a[s]) * vq[c][s];
-            int t = s0 + R + Q - s;
-            t = t >= QD ? t - QD : t;
-            sm += T(S::a[s]) * ring[(t * 3 + c) * NT + tid];
+            if constexpr (RL) {
+              if (s == 0) {
+                sm += T(S::a[s]) * flead[RL ? c : 0];
+              } else {
+                int t = s0 + R + Q - s;
+                t = t >= NR ? t - NR : t;
+                sm += T(S::a[s]) * ring[(t * 3 + c) * NT + tid];
+              }
+            } else {
+              int t = s0 + R + Q - s;
+              t = t >= QD ? t - QD : t;
+              sm += T(S::a[s]) * ring[(t * 3 + c) * NT + tid];
+            }
           }
           u[2][c] = sp * ihs;
           dv[c] -= sm * ihs;
@@ -846,9 +875,18 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
       const T* r = lead_raw;  // sigma (6), M_s (3) of plane a + 1 + R
       T f[3];
       flux3(r[6], r[7], r[8], r[0], r[1], r[2], r[3], r[4], r[5], f);
-      const int sl = slot(a + 1 + R);
+      if constexpr (RL) {  // plane a + R joins the ring in the slot of plane a - Q
+        const int sl = slot(a + R);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) ring[(sl * 3 + c) * NT + tid] = f[c];
+        for (int c = 0; c < 3; ++c) {
+          ring[(sl * 3 + c) * NT + tid] = flead[RL ? c : 0];
+          flead[RL ? c : 0] = f[c];
+        }
+      } else {
+        const int sl = slot(a + 1 + R);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ring[(sl * 3 + c) * NT + tid] = f[c];
+      }
       if constexpr (SR) {  // plane a's slot is free now: it takes plane a + 1 + R
         const int ss = (a + 1 + R) % SD;
 #pragma unroll
@@ -1207,7 +1245,9 @@ struct PersistOrders<float> {
 };
 template <>
 struct PersistOrders<double> {
-  static constexpr int lo = 2, hi = 6;  // order 7's stage tile exceeds the LDS in double
+  // order 7 takes grouped launches: its tile fills the LDS, which would
+  // then be the size of every block of the kernel
+  static constexpr int lo = 2, hi = 6;
 };
 
 // the orders a kernel serves: bit o of MASK
@@ -1450,7 +1490,7 @@ __global__ void energy_kernel(EnergyArgs<T> E) {
 
 // ---------------------------------------------------------------------------
 // launchers (a stage body whose LDS does not fit is not built: 16-row tiles
-// and orders 7 and 8 in double, order 8 with 16-row tiles)
+// and order 8 in double, order 8 with 16-row tiles)
 template <typename T, int ORDER, int TY>
 static hipError_t launch_stage_t(const StageArgs<T>& a, hipStream_t st) {
   if constexpr (!stage_built<T, ORDER, TY>()) {

@@ -54,6 +54,7 @@ ADJ_RHS_CASES = [
     (6, (13, 17, 65), "f64", 1),   # last q column and last r row on the edge kernel
     (4, (11, 17, 65), "f32", 0),
     (6, (13, 12, 40), "f32", 1),
+    (7, (14, 15, 65), "f64", 1),   # order 7 in double, edge-kernel shape
     (8, (16, 17, 65), "f32", 0),   # order 8 (FP32 only), edge-kernel shape
 ]
 

@@ -106,11 +106,17 @@ RHS_CASES = [
     (5, (17, 13, 131), "f32", 1),
     (5, (15, 25, 97), "f64", 0),
     (3, (14, 33, 129), "f64", 1),
-    # interior order 7 (FP32 only: its double-precision tiles exceed the LDS)
+    # interior order 7 (double precision: the s-flux ring with its newest
+    # plane in registers)
     (7, (14, 14, 14), "f32", 0),
     (7, (17, 19, 70), "f32", 1),
     (7, (15, 25, 97), "f32", 0),
-    # interior order 8 (FP32 only): minimum size, ragged multi-tile shapes,
+    (7, (14, 14, 14), "f64", 1),
+    (7, (17, 19, 70), "f64", 0),
+    (7, (15, 25, 97), "f64", 1),
+    (7, (18, 21, 65), "f64", 0),
+    # interior order 8 (FP32 only: its double-precision tile exceeds the
+    # LDS): minimum size, ragged multi-tile shapes,
     # edge-kernel shape
     (8, (16, 16, 16), "f32", 0),
     (8, (17, 19, 70), "f32", 1),
@@ -152,8 +158,7 @@ def test_rhs_parity(order, shape, dtype, variant):
 
 @pytest.mark.parametrize("dtype,order,size", [(d, o, sz) for d in ("f64", "f32")
                                               for o, sz in ((6, (49, 45, 37)), (6, (65, 41, 33)), (3, (65, 41, 33)),
-                                                            (5, (49, 45, 37)))] + [("f32", 7, (65, 41, 33)),
-                                                                                    ("f32", 8, (65, 41, 33))])
+                                                            (5, (49, 45, 37)), (7, (65, 41, 33)))] + [("f32", 8, (65, 41, 33))])
 def test_topo_layer_small_100_steps(dtype, order, size):
     """The curvilinear layered workload (topography, transfinite mesh, soft
     layer over a half-space, Ricker moment source, surface receivers) at a
