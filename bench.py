@@ -610,7 +610,7 @@ def main():
                          copy_ceiling_gbs=round(ceiling, 1),
                          frac_of_copy_ceiling=round(m["roofline"]["achieved"] / ceiling, 4)),
     }
-    if not args.no_fp64 and args.dtype == "f32" and order <= 7:  # order 8 is built in FP32 only
+    if not args.no_fp64 and args.dtype == "f32":
         # the same workload in the paper's arithmetic (double precision)
         m64 = measure_topo(args, wl, "f64", order, sbp, torch, np, dev)
         t64 = read_traffic("hbm_bytes_per_launch_f64") if order == 6 else None

@@ -97,8 +97,7 @@ int sbp_workspace_bytes(int nq, int nr, int ns, int order, int dtype, size_t* by
  *               conservative cofactor form of J dxi/dx); a non-positive
  *               Jacobian anywhere is SBP_EINVAL.
  *  order        interior order of accuracy of the upwind pair, 2 to 8
- *               (Table tab:upwind; 8 with SBP_F32 only, whose tile fits
- *               the LDS; 9 is SBP_EINVAL).  The boundary closures are accurate to
+ *               (Table tab:upwind; 9 is SBP_EINVAL).  The boundary closures are accurate to
  *               order order / 2 (rounded down); the paper does not print
  *               them: the library constructs them from the SBP and upwind
  *               properties of Sec. 4.1, the entries those leave free fixed

@@ -171,8 +171,6 @@ int check_dims(int nq, int nr, int ns, int order, int dtype) {
   if (order == 9)
     return fail(SBP_EINVAL, "order 9 is not supported: no boundary closure is constructed for it");
   if (order < 2 || order > 8) return fail(SBP_EINVAL, "order must be 2 to 8 (got %d)", order);
-  if (order == 8 && dtype == SBP_F64)
-    return fail(SBP_EINVAL, "order 8 runs in SBP_F32 only: its double-precision stage tile exceeds the LDS");
   if (dtype != SBP_F32 && dtype != SBP_F64) return fail(SBP_EINVAL, "dtype must be SBP_F32 or SBP_F64");
   const int mn = 2 * order;
   if (nq < mn || nr < mn || ns < mn)

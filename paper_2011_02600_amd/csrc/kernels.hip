@@ -220,14 +220,16 @@ struct StageLds {
   static constexpr std::size_t n_tq = 2 * QROWS * NC;
   static constexpr std::size_t n_lv = 3 * VX * VY, n_lq = 3 * QX * TY, n_lr = 3 * RX * VY;
   // s-flux ring: F_s of the QD planes a - Q .. a + R that D-_s at plane a
-  // reads.  Where that ring leaves the LDS short (double precision, order
-  // 7), the newest plane a + R stays in registers and the ring keeps QD - 1
-  // planes (RL)
-  static constexpr bool RL =
-      sizeof(T) == 8 && TY == 8 &&
-      sizeof(T) * (n_lv + n_lq + n_lr + (std::size_t)QD * 3 * NT + kClosureTab * kMaxM * kMaxCols + n_tq) >
-          kLdsBytes;
-  static constexpr int NR = RL ? QD - 1 : QD;
+  // reads.  Where that ring leaves the LDS short (double precision, orders 7
+  // and 8), the NL newest planes stay in registers and the ring keeps the
+  // QD - NL older ones
+  static constexpr std::size_t fixed = n_lv + n_lq + n_lr + kClosureTab * kMaxM * kMaxCols + n_tq + kNumFaceCoef * TY;
+  static constexpr int NL = (sizeof(T) != 8 || TY != 8) ? 0
+                            : sizeof(T) * (fixed + (std::size_t)QD * 3 * NT) <= kLdsBytes ? 0
+                            : sizeof(T) * (fixed + (std::size_t)(QD - 1) * 3 * NT) <= kLdsBytes ? 1
+                            : sizeof(T) * (fixed + (std::size_t)(QD - 2) * 3 * NT) <= kLdsBytes ? 2
+                                                                                           : 3;
+  static constexpr int NR = QD - NL;
   static constexpr std::size_t n_ring = (std::size_t)NR * 3 * NT;
   static constexpr std::size_t base_bytes = sizeof(T) * (n_lv + n_lq + n_lr + n_ring);
   static constexpr bool SR = base_bytes + sizeof(T) * SD * 9 * NT <= kLdsBytes;
@@ -368,8 +370,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
     flux3(m0, m1, m2, sxx, syy, szz, sxy, sxz, syz, f);
   };
   // ring slot of plane k (k >= -Q)
-  constexpr int NR = L::NR;
-  constexpr bool RL = L::RL;
+  constexpr int NR = L::NR, NL = L::NL;
   auto slot = [&](int k) { return (k + 7 * NR) % NR; };
 
   __syncthreads();  // closure and weight rows written, windows zeroed
@@ -429,9 +430,10 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   }
 
   // register queue vq[s] = v(a - R + s); ring holds F_s(a - Q .. a + R)
-  // (with RL: a - Q .. a + R - 1, and flead F_s(a + R))
+  // (with NL lead planes in registers: a - Q .. a + R - NL, and flead[k]
+  // = F_s(a + R - NL + 1 + k))
   T vq[3][QD];
-  T flead[RL ? 3 : 1] = {};
+  T flead[NL > 0 ? NL : 1][3] = {};
 #pragma unroll
   for (int s = 0; s < QD; ++s)
 #pragma unroll
@@ -462,9 +464,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
           for (int c = 0; c < 9; ++c) sring[((kf % SD) * 9 + c) * NT + tid] = r[c];
         }
       }
-      if (RL && s == QD - 1) {
+      if (NL > 0 && s >= QD - NL) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) flead[RL ? c : 0] = f[c];
+        for (int c = 0; c < 3; ++c) flead[NL > 0 ? s - (QD - NL) : 0][c] = f[c];
       } else {
 #pragma unroll
         for (int c = 0; c < 3; ++c) ring[(slot(kf) * 3 + c) * NT + tid] = f[c];
@@ -577,7 +579,11 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   for (int c = 0; c < 9; ++c) p_dq[c] = T(0);
 #pragma unroll
   for (int c = 0; c < 3; ++c) p_mat[c] = T(0);
-  load_plane(z0);
+  // with lead planes of the s-flux ring in registers (double precision,
+  // order 8) the plane's own values are loaded when it starts, not a plane
+  // ahead
+  constexpr bool PF = NL < 2;
+  if constexpr (PF) load_plane(z0);
 
   // results of the previous plane, stored after the next plane's loads have
   // been issued: loads and stores share one counter, and a wait for a load
@@ -602,8 +608,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   for (int a = z0; a < z1; ++a) {
     const unsigned pa = (unsigned)a * plane;
     const unsigned o = pa + col;
+    if constexpr (!PF) load_plane(a);
     if constexpr (!HALO_AHEAD) load_halo(a);
-    if constexpr (!LATE_AHEAD) load_late(a);
+    if constexpr (!LATE_AHEAD && PF) load_late(a);
     // s closure terms of a closure plane: loaded when the plane starts in
     // single precision, where they are used in double precision
     constexpr bool SCL_EARLY = sizeof(T) == 4;
@@ -716,7 +723,18 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
     // Plane indices are clamped so that the loads need no branch; clamped
     // values belong to planes >= ns, which no interior plane reads.
     T lead_v[3], lead_raw[9];
-    {
+    auto load_lead = [&]() {
+      const unsigned cl = ing ? col : 0u;
+      const unsigned ov = (unsigned)min(a + 1 + Q, ns - 1) * plane + cl;
+      const unsigned of = (unsigned)min(a + 1 + R, ns - 1) * plane + cl;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) lead_v[c] = gq.ld(c, ov);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) lead_raw[c] = gq.ld(3 + c, of);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) lead_raw[6 + c] = gc.ld(6 + c, of);
+    };
+    if constexpr (PF) {
       const unsigned cl = ing ? col : 0u;
       const unsigned ov = (unsigned)min(a + 1 + Q, ns - 1) * plane + cl;
       const unsigned of = (unsigned)min(a + 1 + R, ns - 1) * plane + cl;
@@ -727,7 +745,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
 #pragma unroll
       for (int c = 0; c < 3; ++c) lead_raw[6 + c] = gc.ld(6 + c, of);
     }
-    load_plane(min(a + 1, ns - 1));   // the last plane's prefetch is unused
+    if constexpr (PF) load_plane(min(a + 1, ns - 1));   // the last plane's prefetch is unused
     flush_stores();                   // after every load of the plane
 
     // ---------------- phase 2
@@ -795,9 +813,9 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
 #pragma unroll
           for (int s = 0; s < QD; ++s) {
             sp += T(S::a[s]) * vq[c][s];
-            if constexpr (RL) {
-              if (s == 0) {
-                sm += T(S::a[s]) * flead[RL ? c : 0];
+            if constexpr (NL > 0) {
+              if (s < NL) {
+                sm += T(S::a[s]) * flead[NL > 0 ? NL - 1 - s : 0][c];
               } else {
                 int t = s0 + R + Q - s;
                 t = t >= NR ? t - NR : t;
@@ -821,6 +839,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
         }
       }
 
+      if constexpr (!PF) load_late(a);   // without prefetch: loaded where used
       if constexpr (!LATE_AHEAD) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) dqo[c] = rdq ? p_dq[c] : T(0);
@@ -862,6 +881,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
     }
     st_pend = true;
     __syncthreads();
+    if constexpr (!PF) load_lead();
 
     // advance the s queues to plane a + 1 (the ring slot of plane a - Q
     // becomes that of plane a + 1 + R; each thread touches only its own slots)
@@ -875,12 +895,14 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
       const T* r = lead_raw;  // sigma (6), M_s (3) of plane a + 1 + R
       T f[3];
       flux3(r[6], r[7], r[8], r[0], r[1], r[2], r[3], r[4], r[5], f);
-      if constexpr (RL) {  // plane a + R joins the ring in the slot of plane a - Q
-        const int sl = slot(a + R);
+      if constexpr (NL > 0) {  // the oldest lead plane joins the ring in the slot of plane a - Q
+        const int sl = slot(a + R - NL + 1);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          ring[(sl * 3 + c) * NT + tid] = flead[RL ? c : 0];
-          flead[RL ? c : 0] = f[c];
+          ring[(sl * 3 + c) * NT + tid] = flead[0][c];
+#pragma unroll
+          for (int k = 0; k + 1 < NL; ++k) flead[k][c] = flead[k + 1][c];
+          flead[NL > 0 ? NL - 1 : 0][c] = f[c];
         }
       } else {
         const int sl = slot(a + 1 + R);
@@ -1490,7 +1512,7 @@ __global__ void energy_kernel(EnergyArgs<T> E) {
 
 // ---------------------------------------------------------------------------
 // launchers (a stage body whose LDS does not fit is not built: 16-row tiles
-// and order 8 in double, order 8 with 16-row tiles)
+// in double, order 8 with 16-row tiles)
 template <typename T, int ORDER, int TY>
 static hipError_t launch_stage_t(const StageArgs<T>& a, hipStream_t st) {
   if constexpr (!stage_built<T, ORDER, TY>()) {

@@ -55,7 +55,8 @@ ADJ_RHS_CASES = [
     (4, (11, 17, 65), "f32", 0),
     (6, (13, 12, 40), "f32", 1),
     (7, (14, 15, 65), "f64", 1),   # order 7 in double, edge-kernel shape
-    (8, (16, 17, 65), "f32", 0),   # order 8 (FP32 only), edge-kernel shape
+    (8, (16, 17, 65), "f32", 0),   # order 8, edge-kernel shape
+    (8, (17, 16, 66), "f64", 1),
 ]
 
 

@@ -324,19 +324,19 @@ BATCH_ORACLE_CASES = {
     # an order-8 shot (not built into the work-list kernel) sends the whole
     # batch to one stage and one edge launch per order
     "grouped": [((19, 17, 21), 4), ((17, 18, 19), 8), ((17, 25, 19), 3)],
-    # likewise an order-7 shot in double precision
-    "grouped7": [((19, 17, 21), 4), ((17, 18, 19), 7), ((17, 25, 19), 3)],
+    # likewise order-7 and order-8 shots in double precision
+    "grouped78": [((19, 17, 21), 4), ((17, 18, 19), 7), ((17, 25, 19), 3), ((18, 17, 17), 8)],
 }
 
 
 @pytest.mark.parametrize("dtype,kind", [("f64", "worklist"), ("f32", "worklist"), ("f32", "grouped"),
-                                        ("f64", "grouped7")])
+                                        ("f64", "grouped78")])
 def test_batch_against_oracle(dtype, kind):
     """sbp_step_batch on shots of uneven size and mixed interior orders, each
     with its own random medium, source and receivers: 40 steps, every shot's
     state and traces against the oracle (work-list launches for orders 3-6,
     grouped launches when an order-8 shot, or in double precision an order-7
-    shot, is present)."""
+    or order-8 shot, is present)."""
     sbp = sbp_mod()
     cases = BATCH_ORACLE_CASES[kind]
     say("case: batch vs oracle %s %s" % (dtype, kind))

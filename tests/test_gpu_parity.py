@@ -115,13 +115,17 @@ RHS_CASES = [
     (7, (17, 19, 70), "f64", 0),
     (7, (15, 25, 97), "f64", 1),
     (7, (18, 21, 65), "f64", 0),
-    # interior order 8 (FP32 only: its double-precision tile exceeds the
-    # LDS): minimum size, ragged multi-tile shapes,
-    # edge-kernel shape
+    # interior order 8: minimum size, ragged multi-tile shapes, edge-kernel
+    # shape (double precision: three lead planes of the s-flux ring in
+    # registers, no prefetch)
     (8, (16, 16, 16), "f32", 0),
     (8, (17, 19, 70), "f32", 1),
     (8, (18, 25, 97), "f32", 0),
     (8, (17, 17, 65), "f32", 1),
+    (8, (16, 16, 16), "f64", 1),
+    (8, (17, 19, 70), "f64", 0),
+    (8, (18, 25, 97), "f64", 1),
+    (8, (17, 17, 65), "f64", 0),
 ]
 
 
@@ -158,7 +162,7 @@ def test_rhs_parity(order, shape, dtype, variant):
 
 @pytest.mark.parametrize("dtype,order,size", [(d, o, sz) for d in ("f64", "f32")
                                               for o, sz in ((6, (49, 45, 37)), (6, (65, 41, 33)), (3, (65, 41, 33)),
-                                                            (5, (49, 45, 37)), (7, (65, 41, 33)))] + [("f32", 8, (65, 41, 33))])
+                                                            (5, (49, 45, 37)), (7, (65, 41, 33)), (8, (65, 41, 33)))])
 def test_topo_layer_small_100_steps(dtype, order, size):
     """The curvilinear layered workload (topography, transfinite mesh, soft
     layer over a half-space, Ricker moment source, surface receivers) at a

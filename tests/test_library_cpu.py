@@ -38,7 +38,7 @@ def test_workspace_size_and_validation():
     assert b >= 39 * n
     b32 = sbp.sbp_workspace_bytes(21, 21, 21, 4, sbp.SBP_F32)
     assert b32 < b
-    for args in [(7, 21, 21, 4, sbp.SBP_F64), (21, 21, 11, 6, sbp.SBP_F32), (21, 21, 21, 8, sbp.SBP_F64),
+    for args in [(7, 21, 21, 4, sbp.SBP_F64), (21, 21, 11, 6, sbp.SBP_F32), (21, 21, 15, 8, sbp.SBP_F64),
                  (21, 21, 15, 8, sbp.SBP_F32),
                  (21, 21, 21, 9, sbp.SBP_F32), (21, 21, 21, 10, sbp.SBP_F32), (21, 21, 13, 7, sbp.SBP_F64),
                  (21, 21, 21, 1, sbp.SBP_F32), (21, 21, 9, 5, sbp.SBP_F64), (21, 21, 13, 7, sbp.SBP_F32),
@@ -49,8 +49,7 @@ def test_workspace_size_and_validation():
     # minimum sizes are accepted
     for order in (2, 3, 4, 5, 6, 7, 8):
         sbp.sbp_workspace_bytes(2 * order, 2 * order, 2 * order, order, sbp.SBP_F32)
-        if order <= 7:
-            sbp.sbp_workspace_bytes(2 * order, 2 * order, 2 * order, order, sbp.SBP_F64)
+        sbp.sbp_workspace_bytes(2 * order, 2 * order, 2 * order, order, sbp.SBP_F64)
 
 
 def test_field_size_limit():
