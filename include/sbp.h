@@ -229,8 +229,9 @@ int sbp_set_graphs(sbp_handle h, int on);
  * 8-row tiles and one s-chunk length for the batch (from
  * sbp_autotune_batch, else a cost model); the handles' own launch settings
  * are restored on return.  With plain addressing on any handle
- * (sbp_set_addressing), one stage and one edge launch per interior order
- * replace the work-list launch.  Each handle's state, time, step count and
+ * (sbp_set_addressing), or with a handle of an order the work-list kernel
+ * does not serve (order 8; orders 7 and 8 in SBP_F64), one stage and one
+ * edge launch per interior order replace the work-list launch.  Each handle's state, time, step count and
  * receiver traces end up as after sbp_step(hs[i], nsteps, dt[i]), to
  * rounding (the batched kernels are separate instantiations of the same
  * kernel bodies).  All handles need the same dtype and the same stream,

@@ -723,6 +723,8 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
     // Plane indices are clamped so that the loads need no branch; clamped
     // values belong to planes >= ns, which no interior plane reads.
     T lead_v[3], lead_raw[9];
+    // (without prefetch the same loads are issued at the end of the plane,
+    // so that their values do not hold registers through the derivatives)
     auto load_lead = [&]() {
       const unsigned cl = ing ? col : 0u;
       const unsigned ov = (unsigned)min(a + 1 + Q, ns - 1) * plane + cl;
