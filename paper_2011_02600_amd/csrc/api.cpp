@@ -90,7 +90,7 @@ struct sbp_ctx {
   std::size_t ws_bytes = 0;
   // byte offsets in the workspace
   std::size_t off_qa = 0, off_qb = 0, off_dq = 0, off_coef = 0, off_face[6] = {}, off_src = 0,
-              off_rec = 0, off_part = 0, off_bounds = 0, off_tab = 0, off_scl = 0, off_batch = 0,
+              off_rec = 0, off_part = 0, off_bounds = 0, off_tab = 0, off_scl = 0, off_eqc = 0, off_batch = 0,
               total = 0;
   std::size_t face_n[6] = {};
   int px = 0;
@@ -221,6 +221,10 @@ BatchRegion batch_region() {
 }
 std::size_t batch_region_bytes() { return batch_region().total; }
 
+// elements of the single-precision copies of the last column's q closure
+// inputs: 8 values x ns planes x nr rows x (kMaxCols - 1) columns
+std::size_t eqc_elems(int nr, int ns) { return (std::size_t)8 * ns * nr * (kMaxCols - 1); }
+
 void layout(sbp_ctx* h) {
   const int es = h->esize;
   const Geometry& g = h->g;
@@ -254,6 +258,9 @@ void layout(sbp_ctx* h) {
   h->off_bounds = take((std::size_t)(g.nq + g.nr + g.ns + 16) * sizeof(int));
   h->off_tab = take((std::size_t)kClosureTab * kMaxM * kMaxCols * es);
   h->off_scl = take((std::size_t)2 * kMaxM * 6 * h->plane * es);
+  // single precision: the stage kernel's copies of the last column's q
+  // closure inputs (StageArgs::eqc), sized for the widest closure row
+  h->off_eqc = take(es == 4 ? eqc_elems(g.nr, g.ns) * es : 0);
   h->off_batch = take(batch_region_bytes());
   h->tab_part_bytes = align256((std::size_t)kTabSteps * 5 * kMaxSources * es);
   h->off_clock = take(sizeof(StepClock));
@@ -523,6 +530,7 @@ StageArgs<T> stage_args(sbp_ctx* h) {
   a.inv_h[2] = (T)(g.ns - 1);
   a.tab = (const T*)(h->ws + h->off_tab);
   a.scl = (T*)(h->ws + h->off_scl);
+  a.eqc = sizeof(T) == 4 ? (T*)(h->ws + h->off_eqc) : nullptr;
   return a;
 }
 
@@ -875,7 +883,10 @@ int batch_upload(sbp_ctx** hs, int n, const double* dt, bool rhs_only, BatchPlan
   std::vector<StageArgs<T>> sa((std::size_t)10 * kMaxBatch);
   for (int g = 0; g < n; ++g) {
     sbp_ctx* h = hs[g];
-    const StageArgs<T> a = stage_args<T>(h);
+    StageArgs<T> a = stage_args<T>(h);
+    // the work list runs stage tiles and edge blocks in one launch: the edge
+    // blocks gather the last column's closure inputs themselves
+    a.eqc = nullptr;
     for (int k = 0; k < 5; ++k)
       for (int p = 0; p < 2; ++p)
         sa[(std::size_t)(k * 2 + p) * kMaxBatch + g] = stage_entry<T>(h, a, k, h->cur ^ p, dt[g], rhs_only);
@@ -2066,6 +2077,7 @@ int sbp_fill_scratch(sbp_handle h, double value) {
     HIPCHK(launch_fill<float>((float*)other, 9 * h->field, (float)value, h->stream));
     HIPCHK(launch_fill<float>((float*)dq, 9 * h->field, (float)value, h->stream));
     HIPCHK(launch_fill<float>((float*)scl, nscl, (float)value, h->stream));
+    HIPCHK(launch_fill<float>((float*)(h->ws + h->off_eqc), eqc_elems(h->g.nr, h->g.ns), (float)value, h->stream));
   } else {
     HIPCHK(launch_fill<double>((double*)other, 9 * h->field, value, h->stream));
     HIPCHK(launch_fill<double>((double*)dq, 9 * h->field, value, h->stream));

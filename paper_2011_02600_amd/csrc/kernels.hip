@@ -504,6 +504,14 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   // first tile column, lane 0 of each row
   constexpr bool Q0S = q0_in_stage<T>();
   const bool q0pen = Q0S && A.sat != 0 && x0 == 0;
+  // single precision: lanes of the columns nq-NC .. nq-2 copy v and F_q of
+  // their node from LDS to A.eqc for the edge kernel's last-column q closure
+  // rows (after the plane's loads are issued, like the deferred stores), so
+  // that the edge kernel does not gather those columns, a line per row and
+  // field (in double precision that gather costs the edge kernel about as
+  // much as the copies cost this kernel)
+  constexpr bool EQC = sizeof(T) == 4;
+  const bool eql = EQC && A.eqc != nullptr && act && i >= nq - NC;
 
   // prefetch registers: everything plane a needs from memory (own sigma, M,
   // material, Runge-Kutta register; the y-halo and x-halo points of the
@@ -749,6 +757,15 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
     }
     if constexpr (PF) load_plane(min(a + 1, ns - 1));   // the last plane's prefetch is unused
     flush_stores();                   // after every load of the plane
+    if constexpr (EQC) {
+      if (eql) {  // the last column's q closure inputs, from LDS
+        T* const e = A.eqc + 8 * (((std::size_t)a * nr + j) * (NC - 1) + (std::size_t)(i - (nq - NC)));
+        const float4 w0 = make_float4(lv[vme], lv[VX * VY + vme], lv[2 * VX * VY + vme], lq[qme]);
+        const float2 w1 = make_float2(lq[QX * TY + qme], lq[2 * QX * TY + qme]);
+        *reinterpret_cast<float4*>(e) = w0;
+        *reinterpret_cast<float2*>(e + 4) = w1;
+      }
+    }
 
     // ---------------- phase 2
     if (act) {
@@ -1036,6 +1053,8 @@ __device__ __forceinline__ void edge_body(const StageArgs<T>& A, int b, char* ld
     // node's row.  Sixteen lanes per node (lane l: column nq-16+l) load them
     // together, so that a load touches a few lines instead of one per lane,
     // and sum in a fixed butterfly; column nq-1 is added by the node itself.
+    // In the rows the stage tiles compute, v and F_q of those columns come
+    // from the stage kernel's copies (A.eqc), contiguous per row.
     const int grp = tid >> 4, l = tid & 15;
     const int col = nq - 16 + l, cc = 15 - l;  // cc: column index of the closure row
     const T cp = (cc >= 1 && cc < NC) ? ltab[2 * TABN + cc] : T(0);
@@ -1045,14 +1064,26 @@ __device__ __forceinline__ void edge_body(const StageArgs<T>& A, int b, char* ld
       const int tq = t0 + (nd & 63), kq = k0 + nd / 64;
       T pv[3] = {T(0), T(0), T(0)}, pf[3] = {T(0), T(0), T(0)};
       if (tq < Ln && kq < ns && cc >= 1 && cc < NC && col >= 0) {
-        const long long op = nm(col, tq, kq);
-        T f[3];
-        flux3(cf[op], cf[field + op], cf[2 * field + op], qin[3 * field + op], qin[4 * field + op],
-              qin[5 * field + op], qin[6 * field + op], qin[7 * field + op], qin[8 * field + op], f);
+        if (A.eqc != nullptr && tq < nr - ey) {
+          const T* const e = A.eqc + 8 * (((std::size_t)kq * nr + tq) * (NC - 1) + (std::size_t)(NC - 1 - cc));
+          T w[6];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          pv[c] = cp * qin[c * field + op];
-          pf[c] = cm * f[c];
+          for (int c = 0; c < 6; ++c) w[c] = e[c];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            pv[c] = cp * w[c];
+            pf[c] = cm * w[3 + c];
+          }
+        } else {
+          const long long op = nm(col, tq, kq);
+          T f[3];
+          flux3(cf[op], cf[field + op], cf[2 * field + op], qin[3 * field + op], qin[4 * field + op],
+                qin[5 * field + op], qin[6 * field + op], qin[7 * field + op], qin[8 * field + op], f);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            pv[c] = cp * qin[c * field + op];
+            pf[c] = cm * f[c];
+          }
         }
       }
 #pragma unroll

@@ -21,6 +21,13 @@ struct StageArgs {
   // kernel: value (side, row, c) of node col at ((side * kMaxM + row) * 6 +
   // c) * plane + col; c = 0..2: h D+_s v_c, 3..5: h D-_s F_s,c
   T* scl;
+  // v and the q flux F_q of the columns nq-NC .. nq-2 (the ones the q
+  // closure row of the last column reads), written by the stage kernel for
+  // the edge kernel of the same stage (single precision): 8 values per node
+  // (v 0..2, F_q 3..5, 2 unused), node (i, j, k) at 8 * ((k * nr + j) *
+  // (NC - 1) + i - (nq - NC)).  NULL: the edge kernel gathers those columns
+  // itself (double precision; stage and edge blocks in one launch)
+  T* eqc;
   NodeMap nm;         // node -> element offset in a field
   std::size_t face_off[6];
   std::size_t face_n[6];
