@@ -247,7 +247,9 @@ constexpr bool stage_built() {
   return StageLds<T, ORDER, TY>::bytes <= kLdsBytes;
 }
 
-template <typename T, int ORDER, int TY, bool BUF>
+// EQ: the copies for the edge kernel (StageArgs::eqc) are built in (the
+// single-grid kernel; batched launches gather instead)
+template <typename T, int ORDER, int TY, bool BUF, bool EQ = false>
 __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile, char* lds) {
   using S = Stencil<ORDER>;
   using L = StageLds<T, ORDER, TY>;
@@ -510,7 +512,7 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
   // that the edge kernel does not gather those columns, a line per row and
   // field (in double precision that gather costs the edge kernel about as
   // much as the copies cost this kernel)
-  constexpr bool EQC = sizeof(T) == 4;
+  constexpr bool EQC = EQ && sizeof(T) == 4;
   const bool eql = EQC && A.eqc != nullptr && act && i >= nq - NC;
 
   // prefetch registers: everything plane a needs from memory (own sigma, M,
@@ -965,7 +967,7 @@ struct EdgeLds {
   static constexpr std::size_t bytes = total * sizeof(T);
 };
 
-template <typename T, int ORDER, int KZ>
+template <typename T, int ORDER, int KZ, bool EQ = false>
 __device__ __forceinline__ void edge_body(const StageArgs<T>& A, int b, char* lds) {
   using S = Stencil<ORDER>;
   using L = EdgeLds<T, ORDER, KZ>;
@@ -1064,7 +1066,7 @@ __device__ __forceinline__ void edge_body(const StageArgs<T>& A, int b, char* ld
       const int tq = t0 + (nd & 63), kq = k0 + nd / 64;
       T pv[3] = {T(0), T(0), T(0)}, pf[3] = {T(0), T(0), T(0)};
       if (tq < Ln && kq < ns && cc >= 1 && cc < NC && col >= 0) {
-        if (A.eqc != nullptr && tq < nr - ey) {
+        if (EQ && A.eqc != nullptr && tq < nr - ey) {
           const T* const e = A.eqc + 8 * (((std::size_t)kq * nr + tq) * (NC - 1) + (std::size_t)(NC - 1 - cc));
           T w[6];
 #pragma unroll
@@ -1245,13 +1247,13 @@ __global__ __launch_bounds__(64 * TY, SBP_STAGE_MIN_WAVES) void stage_kernel(con
   __shared__ __align__(16) char lds[StageLds<T, ORDER, TY>::bytes];
   // XCD-aware tile order: consecutive tiles land on the same XCD
   const int per = gridDim.x >> 3;
-  stage_body<T, ORDER, TY, BUF>(A, (blockIdx.x & 7) * per + (blockIdx.x >> 3), lds);
+  stage_body<T, ORDER, TY, BUF, true>(A, (blockIdx.x & 7) * per + (blockIdx.x >> 3), lds);
 }
 
 template <typename T, int ORDER, int KZ>
 __global__ __launch_bounds__(64 * KZ) void edge_kernel(const StageArgs<T> A) {
   __shared__ __align__(16) char lds[EdgeLds<T, ORDER, KZ>::bytes];
-  edge_body<T, ORDER, KZ>(A, blockIdx.x, lds);
+  edge_body<T, ORDER, KZ, true>(A, blockIdx.x, lds);
 }
 
 // last entry of first[0 .. n-1] (non-decreasing, first[0] = 0) that is <= item
