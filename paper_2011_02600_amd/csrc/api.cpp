@@ -575,6 +575,18 @@ StageArgs<T> stage_entry(sbp_ctx* h, const StageArgs<T>& a, int k, int c, double
   return b;
 }
 
+// The launches that follow the stage kernel of one grid: the edge kernel
+// (when the tiles leave a last column or row) and the boundary penalties (when
+// a.sat).  In single precision both go in one launch.
+template <typename T>
+hipError_t edge_and_penalties(const sbp_ctx* h, const StageArgs<T>& a, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (sizeof(T) == 4 && a.sat && (h->ex || h->ey)) return launch_edge_penalty<T>(h->order, a, st);
+  if (h->ex || h->ey) e = launch_edge<T>(h->order, a, st);
+  if (e == hipSuccess && a.sat) e = launch_penalty<T>(a, st);
+  return e;
+}
+
 // One Runge-Kutta stage (or the right-hand side alone) on stream st: the
 // stage kernel, the edge kernel, the boundary penalties, the point sources
 // (dt * g from the clock's table when clock is not null, else evaluated here
@@ -590,8 +602,7 @@ int run_stage(sbp_ctx* h, StageArgs<T>& a, int k, double dt, double tstage, bool
   if (prof) HIPCHK(hipEventRecord(h->ev[0], st));
   HIPCHK(launch_stage<T>(h->order, h->ty, a, st));
   if (prof) HIPCHK(hipEventRecord(h->ev[1], st));
-  if (h->ex || h->ey) HIPCHK(launch_edge<T>(h->order, a, st));
-  if (a.sat) HIPCHK(launch_penalty<T>(a, st));
+  HIPCHK(edge_and_penalties<T>(h, a, st));
   if (prof) {
     HIPCHK(hipEventRecord(h->ev[2], st));
     HIPCHK(hipEventSynchronize(h->ev[2]));
@@ -1418,8 +1429,7 @@ int stage_explicit(sbp_ctx* h, const StageArgs<T>& base, int k, double dt, doubl
   b.coef = coef;
   b.sat = sat ? 1 : 0;
   HIPCHK(launch_stage<T>(h->order, h->ty, b, h->stream));
-  if (h->ex || h->ey) HIPCHK(launch_edge<T>(h->order, b, h->stream));
-  if (sat) HIPCHK(launch_penalty<T>(b, h->stream));
+  HIPCHK(edge_and_penalties<T>(h, b, h->stream));
   if (sources && !h->src.empty()) {
     SourceArgs<T> s = source_args<T>(h, k, dt, tstage, rhs_only, qout);
     s.dq = dq;

@@ -967,7 +967,9 @@ struct EdgeLds {
   static constexpr std::size_t bytes = total * sizeof(T);
 };
 
-template <typename T, int ORDER, int KZ, bool EQ = false>
+// PEN: the boundary penalties of the strip's nodes are added here (before
+// the stage update) instead of by penalty_kernel
+template <typename T, int ORDER, int KZ, bool EQ = false, bool PEN = false>
 __device__ __forceinline__ void edge_body(const StageArgs<T>& A, int b, char* lds) {
   using S = Stencil<ORDER>;
   using L = EdgeLds<T, ORDER, KZ>;
@@ -1223,7 +1225,24 @@ __device__ __forceinline__ void edge_body(const StageArgs<T>& A, int b, char* ld
   T rate[9];
   node_rates(u, dv, mq, mr, ms, cf[9 * field + o], cf[10 * field + o], cf[11 * field + o], rate);
 
-  // the boundary penalties are added by penalty_kernel after the launch
+  // the boundary penalties of every face the node lies on (with PEN; else
+  // penalty_kernel adds them after the launch)
+  if constexpr (PEN) {
+    if (A.sat) {
+      T fc[kNumFaceCoef];
+      auto face = [&](int f, std::size_t idx, T eps) {
+#pragma unroll
+        for (int kk = 0; kk < kNumFaceCoef; ++kk) fc[kk] = A.face[A.face_off[f] + idx + (std::size_t)kk * A.face_n[f]];
+        face_penalty(fc, A.gamma[f], eps, A.traction[f] != 0, v, sg, rate);
+      };
+      if (i == 0) face(0, (std::size_t)k * nr + j, T(-1));
+      if (i == nq - 1) face(1, (std::size_t)k * nr + j, T(1));
+      if (j == 0) face(2, (std::size_t)k * nq + i, T(-1));
+      if (j == nr - 1) face(3, (std::size_t)k * nq + i, T(1));
+      if (k == 0) face(4, (std::size_t)j * nq + i, T(-1));
+      if (k == ns - 1) face(5, (std::size_t)j * nq + i, T(1));
+    }
+  }
 
   const T dt = A.dt, Ak = A.Ak, Bk = A.Bk;
 #pragma unroll
@@ -1254,6 +1273,28 @@ template <typename T, int ORDER, int KZ>
 __global__ __launch_bounds__(64 * KZ) void edge_kernel(const StageArgs<T> A) {
   __shared__ __align__(16) char lds[EdgeLds<T, ORDER, KZ>::bytes];
   edge_body<T, ORDER, KZ, true>(A, blockIdx.x, lds);
+}
+
+// penalty_part and penalty_body are defined further down
+template <typename T>
+__device__ __forceinline__ long long penalty_part(const StageArgs<T>& A, long long e);
+template <typename T>
+__device__ __forceinline__ void penalty_body(const StageArgs<T>& A, long long e);
+
+// single precision: the edge blocks, with the penalties of their own nodes,
+// then the boundary penalties of the nodes the stage tiles computed (the
+// penalty part of those) in the same launch, so that the penalty blocks fill
+// the compute units the edge blocks leave idle
+template <typename T, int ORDER, int KZ>
+__global__ __launch_bounds__(64 * KZ) void edge_penalty_kernel(const StageArgs<T> A, const int eblocks) {
+  __shared__ __align__(16) char lds[EdgeLds<T, ORDER, KZ>::bytes];
+  if ((int)blockIdx.x < eblocks) {
+    edge_body<T, ORDER, KZ, true, true>(A, blockIdx.x, lds);
+  } else {
+    const long long e =
+        penalty_part(A, (long long)(blockIdx.x - eblocks) * (64 * KZ) + threadIdx.y * 64 + threadIdx.x);
+    if (e >= 0) penalty_body(A, e);
+  }
 }
 
 // last entry of first[0 .. n-1] (non-decreasing, first[0] = 0) that is <= item
@@ -1419,6 +1460,29 @@ __device__ __forceinline__ void penalty_body(const StageArgs<T>& A, long long e)
 template <typename T>
 __global__ __launch_bounds__(256) void penalty_kernel(const StageArgs<T> A) {
   penalty_body(A, (long long)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// With the q = 0 face in the stage kernel, penalty_body's enumeration is the
+// q = nq-1 face [0, nA), the r = 0 face [nA, nA + P), the r = nr-1 face
+// [nA + P, nA + 2P), the s faces after (P = (nq-1) ns).  Its part that the
+// stage tiles compute: r = 0, the s faces, and r = nr-1 when there is no
+// edge row.  Index e of that part -> index of the enumeration, or -1 past
+// the part's end.
+template <typename T>
+__device__ __forceinline__ long long penalty_part(const StageArgs<T>& A, long long e) {
+  const long long nA = (long long)A.nr * A.ns, P = (long long)(A.nq - 1) * A.ns;
+  const long long nC = 2LL * (A.nq - 1) * (A.nr - 2);
+  const long long nrf = A.ey ? P : 2 * P;
+  if (e < nrf) return nA + e;
+  e -= nrf;
+  return e < nC ? nA + 2 * P + e : -1;
+}
+
+// number of nodes of that part (host and device)
+template <typename T>
+__host__ __device__ inline long long penalty_part_nodes(const StageArgs<T>& A) {
+  const long long P = (long long)(A.nq - 1) * A.ns, nC = 2LL * (A.nq - 1) * (A.nr - 2);
+  return (A.ey ? P : 2 * P) + nC;
 }
 
 // surface nodes of several grids: thread -> grid by the prefix sums in first
@@ -1605,6 +1669,14 @@ static std::size_t step_scratch_t() {
       hipFuncAttributes at{};
       if (hipFuncGetAttributes(&at, f) != hipSuccess) return (std::size_t)-1;
       m = std::max<std::size_t>(m, at.localSizeBytes);
+    }
+    if constexpr (sizeof(T) == 4) {
+      const void* fe[] = {reinterpret_cast<const void*>(&edge_penalty_kernel<T, ORDER, 8>)};
+      for (const void* f : fe) {
+        hipFuncAttributes at{};
+        if (hipFuncGetAttributes(&at, f) != hipSuccess) return (std::size_t)-1;
+        m = std::max<std::size_t>(m, at.localSizeBytes);
+      }
     }
     return m;
   }
@@ -1793,6 +1865,36 @@ hipError_t launch_penalty(const StageArgs<T>& a, hipStream_t st) {
 }
 
 template <typename T>
+hipError_t launch_edge_penalty(int order, const StageArgs<T>& a, hipStream_t st) {
+  if constexpr (sizeof(T) != 4) {
+    return hipErrorInvalidValue;
+  } else {
+    constexpr int KZ = 8;
+    const int ne = edge_blocks(a);
+    const long long np = penalty_part_nodes(a);
+    const int nb = ne + (int)((np + 64 * KZ - 1) / (64 * KZ));
+    if (nb == 0) return hipSuccess;
+    if (order == 2)
+      hipLaunchKernelGGL((edge_penalty_kernel<T, 2, KZ>), dim3(nb), dim3(64, KZ), 0, st, a, ne);
+    else if (order == 3)
+      hipLaunchKernelGGL((edge_penalty_kernel<T, 3, KZ>), dim3(nb), dim3(64, KZ), 0, st, a, ne);
+    else if (order == 4)
+      hipLaunchKernelGGL((edge_penalty_kernel<T, 4, KZ>), dim3(nb), dim3(64, KZ), 0, st, a, ne);
+    else if (order == 5)
+      hipLaunchKernelGGL((edge_penalty_kernel<T, 5, KZ>), dim3(nb), dim3(64, KZ), 0, st, a, ne);
+    else if (order == 6)
+      hipLaunchKernelGGL((edge_penalty_kernel<T, 6, KZ>), dim3(nb), dim3(64, KZ), 0, st, a, ne);
+    else if (order == 7)
+      hipLaunchKernelGGL((edge_penalty_kernel<T, 7, KZ>), dim3(nb), dim3(64, KZ), 0, st, a, ne);
+    else if (order == 8)
+      hipLaunchKernelGGL((edge_penalty_kernel<T, 8, KZ>), dim3(nb), dim3(64, KZ), 0, st, a, ne);
+    else
+      return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+}
+
+template <typename T>
 hipError_t launch_penalty_batch(const BatchArgs<T>& b, hipStream_t st) {
   if (b.total == 0) return hipSuccess;
   hipLaunchKernelGGL(penalty_kernel_batch<T>, dim3((b.total + 255) / 256), dim3(256), 0, st, b);
@@ -1852,6 +1954,8 @@ template bool worklist_order_ok<float>(int);
 template bool worklist_order_ok<double>(int);
 template hipError_t launch_penalty<float>(const StageArgs<float>&, hipStream_t);
 template hipError_t launch_penalty<double>(const StageArgs<double>&, hipStream_t);
+template hipError_t launch_edge_penalty<float>(int, const StageArgs<float>&, hipStream_t);
+template hipError_t launch_edge_penalty<double>(int, const StageArgs<double>&, hipStream_t);
 template hipError_t launch_penalty_batch<float>(const BatchArgs<float>&, hipStream_t);
 template hipError_t launch_penalty_batch<double>(const BatchArgs<double>&, hipStream_t);
 template hipError_t launch_source<float>(const SourceArgs<float>&, int, hipStream_t);

@@ -181,6 +181,12 @@ hipError_t launch_record_batch(const RecordBatch<T>& b, hipStream_t st);
 // after the stage and edge kernels
 template <typename T>
 hipError_t launch_penalty(const StageArgs<T>& a, hipStream_t st);
+// single precision: the edge kernel and every boundary penalty in one
+// launch (edge blocks with their own nodes' penalties, then blocks for the
+// penalties of the nodes the stage tiles computed), in place of launch_edge
+// and launch_penalty
+template <typename T>
+hipError_t launch_edge_penalty(int order, const StageArgs<T>& a, hipStream_t st);
 // the same for several grids: b.first holds the prefix sums of their
 // surface node counts (surface_nodes)
 template <typename T>
