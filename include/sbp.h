@@ -367,8 +367,9 @@ int sbp_set_addressing(sbp_handle h, int plain);
 /*
  * Launch timing.  sbp_set_profiling(h, 1) resets the counters and from then
  * on brackets every stage-kernel launch (one Runge-Kutta stage of the nodes
- * covered by the tiles) and every edge-kernel launch (the remaining last q
- * column and last r row) with HIP events on the handle's stream; the host
+ * covered by the tiles) and the launches that follow it (the remaining last
+ * q column and last r row, and the boundary penalties: one launch in
+ * SBP_F32) with HIP events on the handle's stream; the host
  * waits for each stage to finish, so stepping is slower while it is on.
  * sbp_set_profiling(h, 0) switches it off.  sbp_profile returns the average
  * durations in milliseconds (*stage_ms, *edge_ms), the number of timed stages
