@@ -531,6 +531,7 @@ StageArgs<T> stage_args(sbp_ctx* h) {
   a.tab = (const T*)(h->ws + h->off_tab);
   a.scl = (T*)(h->ws + h->off_scl);
   a.eqc = sizeof(T) == 4 ? (T*)(h->ws + h->off_eqc) : nullptr;
+  a.nsrc = 0;
   return a;
 }
 
@@ -556,6 +557,29 @@ SourceArgs<T> source_args(sbp_ctx* h, int k, double dt, double tstage, bool rhs_
   s.clock = nullptr;
   s.stage = k;
   return s;
+}
+
+// single precision: the point sources of stage k go into the stage and edge
+// kernels' update (StageArgs::nsrc and src_*), in place of a source_kernel
+// launch; returns whether they did
+template <typename T>
+bool fuse_sources(sbp_ctx* h, StageArgs<T>& a, int k, double dt, double tstage, bool rhs_only,
+                  const StepClock* clock) {
+  a.nsrc = 0;
+  if (sizeof(T) != 4 || h->src.empty()) return false;
+  const SourceArgs<T> s = source_args<T>(h, k, dt, tstage, rhs_only, nullptr);
+  a.nsrc = (int)h->src.size();
+  a.src_w = s.width;
+  a.src_stage = k;
+  for (int i = 0; i < kMaxSources; ++i) {
+    a.src_i0[i] = s.i0[i];
+    a.src_j0[i] = s.j0[i];
+    a.src_k0[i] = s.k0[i];
+    a.src_gdt[i] = s.gdt[i];
+  }
+  a.src_wm = s.wm;
+  a.src_clock = clock;
+  return true;
 }
 
 // arguments of Runge-Kutta stage k (or of the right-hand side alone) with the
@@ -598,6 +622,7 @@ int run_stage(sbp_ctx* h, StageArgs<T>& a, int k, double dt, double tstage, bool
               hipStream_t st, const StepClock* clock) {
   const int c = qin == (T*)(h->ws + h->off_qb) ? 1 : 0;
   a = stage_entry<T>(h, a, k, c, dt, rhs_only);
+  const bool fused = fuse_sources<T>(h, a, k, dt, tstage, rhs_only, clock);
   const bool prof = h->prof && st == h->stream;
   if (prof) HIPCHK(hipEventRecord(h->ev[0], st));
   HIPCHK(launch_stage<T>(h->order, h->ty, a, st));
@@ -613,7 +638,7 @@ int run_stage(sbp_ctx* h, StageArgs<T>& a, int k, double dt, double tstage, bool
     h->prof_edge_ms += t12;
     ++h->prof_n;
   }
-  if (!h->src.empty()) {
+  if (!h->src.empty() && !fused) {
     SourceArgs<T> s = source_args<T>(h, k, dt, tstage, rhs_only, qout);
     s.clock = clock;
     HIPCHK(launch_source<T>(s, (int)h->src.size(), st));
@@ -896,8 +921,10 @@ int batch_upload(sbp_ctx** hs, int n, const double* dt, bool rhs_only, BatchPlan
     sbp_ctx* h = hs[g];
     StageArgs<T> a = stage_args<T>(h);
     // the work list runs stage tiles and edge blocks in one launch: the edge
-    // blocks gather the last column's closure inputs themselves
+    // blocks gather the last column's closure inputs themselves; the sources
+    // follow in source_kernel_batch
     a.eqc = nullptr;
+    a.nsrc = 0;
     for (int k = 0; k < 5; ++k)
       for (int p = 0; p < 2; ++p)
         sa[(std::size_t)(k * 2 + p) * kMaxBatch + g] = stage_entry<T>(h, a, k, h->cur ^ p, dt[g], rhs_only);
@@ -1428,9 +1455,11 @@ int stage_explicit(sbp_ctx* h, const StageArgs<T>& base, int k, double dt, doubl
   b.dt = rhs_only ? T(1) : (T)dt;
   b.coef = coef;
   b.sat = sat ? 1 : 0;
+  const bool fused = sources && fuse_sources<T>(h, b, k, dt, tstage, rhs_only, nullptr);
+  if (!sources) b.nsrc = 0;
   HIPCHK(launch_stage<T>(h->order, h->ty, b, h->stream));
   HIPCHK(edge_and_penalties<T>(h, b, h->stream));
-  if (sources && !h->src.empty()) {
+  if (sources && !fused && !h->src.empty()) {
     SourceArgs<T> s = source_args<T>(h, k, dt, tstage, rhs_only, qout);
     s.dq = dq;
     HIPCHK(launch_source<T>(s, (int)h->src.size(), h->stream));

@@ -249,6 +249,26 @@ constexpr bool stage_built() {
 
 // EQ: the copies for the edge kernel (StageArgs::eqc) are built in (the
 // single-grid kernel; batched launches gather instead)
+// the point-source increments dt g(t) w M of node (i, j, k) (stress
+// components), summed over the sources whose stencil holds it
+template <typename T>
+__device__ __forceinline__ void source_add(const StageArgs<T>& A, int i, int j, int k, T add[6]) {
+  const int w = A.src_w;
+  for (int s = 0; s < A.nsrc; ++s) {
+    const int dk = k - A.src_k0[s], dj = j - A.src_j0[s], di = i - A.src_i0[s];
+    if ((unsigned)dk < (unsigned)w && (unsigned)dj < (unsigned)w && (unsigned)di < (unsigned)w) {
+      const T gdt = A.src_clock
+                        ? static_cast<const T*>(A.src_clock->gtab)[((std::size_t)A.src_clock->step * 5 + A.src_stage) *
+                                                                       kMaxSources + s]
+                        : A.src_gdt[s];
+      const T* wm =
+          A.src_wm + ((std::size_t)s * kMaxSrcWidth * kMaxSrcWidth * kMaxSrcWidth + (dk * w + dj) * w + di) * 6;
+#pragma unroll
+      for (int f = 0; f < 6; ++f) add[f] += gdt * wm[f];
+    }
+  }
+}
+
 template <typename T, int ORDER, int TY, bool BUF, bool EQ = false>
 __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile, char* lds) {
   using S = Stencil<ORDER>;
@@ -884,11 +904,20 @@ __device__ __forceinline__ void stage_body(const StageArgs<T>& A, const int tile
         }
       }
 
+      // point sources whose stencil holds the node (single precision, one grid)
+      T sadd[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+      if constexpr (EQC) {
+        if (A.nsrc > 0) source_add(A, i, j, a, sadd);
+      }
+
       // Runge-Kutta stage update
       const T dt = A.dt, Ak = A.Ak, Bk = A.Bk;
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
-        const T d = dt * rate[c] + Ak * dqo[c];
+        T d = dt * rate[c] + Ak * dqo[c];
+        if constexpr (EQC) {
+          if (c >= 3) d += sadd[c - 3];
+        }
         const T q0 = (c < 3) ? v[c] : sg[c - 3];
         if constexpr (DEFER) {
           st_d[c] = d;
@@ -1244,12 +1273,19 @@ __device__ __forceinline__ void edge_body(const StageArgs<T>& A, int b, char* ld
     }
   }
 
+  T sadd[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+  if constexpr (EQ && sizeof(T) == 4) {
+    if (A.nsrc > 0) source_add(A, i, j, k, sadd);
+  }
   const T dt = A.dt, Ak = A.Ak, Bk = A.Bk;
 #pragma unroll
   for (int c = 0; c < 9; ++c) {
     const long long oc = (long long)c * field + o;
     const T dqo = A.read_dq ? A.dq[oc] : T(0);
-    const T d = dt * rate[c] + Ak * dqo;
+    T d = dt * rate[c] + Ak * dqo;
+    if constexpr (EQ && sizeof(T) == 4) {
+      if (c >= 3) d += sadd[c - 3];
+    }
     const T q0 = (c < 3) ? v[c] : sg[c - 3];
     A.dq[oc] = d;
     A.qout[oc] = q0 + Bk * d;

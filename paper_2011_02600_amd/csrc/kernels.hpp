@@ -9,6 +9,8 @@
 
 namespace sbp {
 
+struct StepClock;
+
 template <typename T>
 struct StageArgs {
   const T* qin;       // 9 fields, current stage input
@@ -28,6 +30,16 @@ struct StageArgs {
   // (NC - 1) + i - (nq - NC)).  NULL: the edge kernel gathers those columns
   // itself (double precision; stage and edge blocks in one launch)
   T* eqc;
+  // point sources that the single-grid stage and edge kernels add at the
+  // stage update (single precision; nsrc = 0: none here, a source_kernel
+  // launch follows instead): stencil width, corners, weights (as
+  // SourceArgs::wm), dt g(t) from the clock's table when src_clock is not
+  // null, else src_gdt
+  int nsrc, src_w, src_stage;
+  int src_i0[kMaxSources], src_j0[kMaxSources], src_k0[kMaxSources];
+  T src_gdt[kMaxSources];
+  const T* src_wm;
+  const StepClock* src_clock;
   NodeMap nm;         // node -> element offset in a field
   std::size_t face_off[6];
   std::size_t face_n[6];
